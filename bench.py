@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the H^2 matrix-vector product on one MI355X.
+
+Workload (default): Laplace single layer on the unit icosphere refined 8 times
+(1,310,720 triangles), tensor Chebyshev interpolation of order 4 (k = 64),
+leaf size 64, admissibility max(diam) <= dist (eta = 1/2), near field by the
+7-point rule with Sauter-Schwab order 4 for touching pairs, coupling, transfer,
+leaf and near-field data stored in FP32 with FP32 accumulation; x ~ N(0,1),
+seed 3.  A step is one full product y <- y + G~ x (forward transformation,
+coupling, backward transformation, near field) with x and y resident in HBM.
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(the coupling phase, HIP events on the launch stream), the same product in FP64
+storage for comparison, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name: (mesh kind, level, order, leaf, storage, seed)
+    "sphere1310k_m4_f32": ("sphere", 8, 4, 64, "f32", 3),
+    "sphere1310k_m4_f64": ("sphere", 8, 4, 64, "f64", 3),
+    "sphere327k_m4_f64": ("sphere", 7, 4, 64, "f64", 2),
+    "cube786k_m4_f32": ("cube", 256, 4, 64, "f32", 4),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def measure(A, x, y, steps, warmup, torch, h2):
+    for _ in range(warmup):
+        A.matvec(x, y)
+    torch.cuda.synchronize()
+    h2.h2_profile(A.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A.matvec(x, y)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = h2.h2_profile_read(A.h)
+    h2.h2_profile(A.h, False)
+    return el, prof
+
+
+def cpu_baseline_sample(kind, level, order, leaf, seed, budget_s=25.0):
+    """Oracle (FP64, Algorithms 1-3 as written) timed on samples of the same workload.
+
+    Forward/backward transformation: Algorithm 1 and 2 on one subtree at depth 5
+    (about 1/32 of the clusters), scaled by the cluster count.  Interaction
+    phase: Algorithm 3 on the admissible and inadmissible leaves of the block
+    rows of a few random leaf clusters (matrices assembled first, then applied
+    and timed), scaled by |L+| and |L-|.
+    """
+    import numpy as np
+
+    import h2_inputs as I
+    from oracle.h2 import H2Oracle
+    from oracle.kernels import Kernel
+
+    V, T = I.mesh_for(kind, level)
+    H = H2Oracle(V, T, Kernel(), m=order, leaf=leaf, eta=0.5, build_blocks=False)
+    x = I.random_vector(H.mesh.n, seed, "normal")
+    ncl = len(H.tree.clusters)
+    sub = H.tree.root
+    while sub.level < 5 and sub.children:
+        sub = sub.children[0]
+    nsub = sum(1 for _ in _walk(sub))
+    xhat = [None] * ncl
+    t0 = time.perf_counter()
+    H.forward(sub, x, xhat)
+    t_fwd = time.perf_counter() - t0
+    yhat = [np.zeros(H.k) if v is None else v.copy() for v in xhat]
+    y = np.zeros(H.mesh.n)
+    t0 = time.perf_counter()
+    H.backward(sub, yhat, y)
+    t_bwd = time.perf_counter() - t0
+    # interaction sample
+    rng = np.random.default_rng(seed)
+    adm, near = [], []
+    t_start = time.perf_counter()
+    for lid in rng.permutation(len(H.tree.leaves)):
+        a, nn = H.row_blocks(H.tree.leaves[lid])
+        adm += a
+        near += nn
+        for t_, s_ in a:
+            H.S(t_, s_)
+            if xhat[s_.id] is None:
+                xhat[s_.id] = np.zeros(H.k)
+        for t_, s_ in nn:
+            H.N(t_, s_)
+        if time.perf_counter() - t_start > 0.6 * budget_s:
+            break
+    yh = np.zeros(H.k)
+    t0 = time.perf_counter()
+    for t_, s_ in adm:
+        yh = yh + H.S(t_, s_) @ xhat[s_.id]
+    t_adm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for t_, s_ in near:
+        y[t_.idx] += H.N(t_, s_) @ x[s_.idx]
+    t_near = time.perf_counter() - t0
+    from paper_2203_05665_amd import h2 as _h2  # structure counts only (host-only build)
+    hh = _h2.build_h2(V, T, order=order, leaf=leaf, eta=0.5, host_only=True)
+    info = _h2.h2_info(hh)
+    _h2.h2_free(hh)
+    est = (t_fwd + t_bwd) * ncl / nsub + t_adm * info["n_adm"] / max(1, len(adm)) + \
+        t_near * info["n_near"] / max(1, len(near))
+    cores = 1
+    try:
+        import threadpoolctl
+        for p in threadpoolctl.threadpool_info():
+            cores = max(cores, int(p.get("num_threads", 1)))
+    except Exception:
+        pass
+    sample = ("oracle Algorithms 1-2 on a depth-5 subtree (%d of %d clusters) and Algorithm 3 on %d "
+              "admissible + %d inadmissible blocks (block rows of random leaves), FP64, matrices pre-assembled; "
+              "scaled to the whole product" % (nsub, ncl, len(adm), len(near)))
+    return {"value": 1.0 / est, "unit": "H2 matvecs/s", "cores": cores, "kind": "oracle",
+            "sample": sample, "est_seconds_per_matvec": est}
+
+
+def _walk(c):
+    yield c
+    for ch in c.children:
+        yield from _walk(ch)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sphere1310k_m4_f32", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the H^2 product here runs on a single MI355X "
+              "(multi-GPU sharding is not implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import h2_inputs as I
+    from paper_2203_05665_amd import h2
+
+    kind, level, order, leaf, storage, seed = WORKLOADS[args.workload]
+    V, T = I.mesh_for(kind, level)
+    n = T.shape[0]
+    log("bench: %s n=%d m=%d leaf=%d storage=%s" % (args.workload, n, order, leaf, storage))
+    t0 = time.perf_counter()
+    A = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = A.info
+    log("bench: built in %.2f s, %.2f GB on device, %d admissible / %d near blocks" %
+        (build_s, info["bytes_total"] / 1e9, info["n_adm"], info["n_near"]))
+    x = torch.tensor(I.random_vector(n, seed, "normal"), dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    el, prof = measure(A, x, y, args.steps, args.warmup, torch, h2)
+    ms_step = 1e3 * el / args.steps
+    sbytes = {"f64": 8, "f32": 4, "f32_sbf16": 2}[storage]
+    coup_bytes = float(info["n_adm"]) * info["k"] ** 2 * sbytes
+    coup_ms, coup_calls = prof["coupling"]
+    coup_avg_ms = coup_ms / max(1, coup_calls)
+    achieved = coup_bytes / (coup_avg_ms * 1e-3) / 1e9
+    log("bench: %.3f ms/matvec; phases %s" % (ms_step, {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()}))
+    out = {
+        "metric": "H2 matvecs/s", "value": args.steps / el, "unit": "matvec/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"f64": "f64", "f32": "f32", "f32_sbf16": "bf16+f32"}[storage],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "mesh": "%s level %d" % (kind, level), "triangles": n,
+                   "order_m": order, "k": order ** 3, "leaf": leaf, "eta": 0.5, "storage": storage,
+                   "accumulate": "f64" if storage == "f64" else "f32", "rhs": 1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "coupling64",
+                     "algorithmic_bytes_per_launch": coup_bytes, "avg_launch_ms": coup_avg_ms},
+        "path": {"algorithmic_bytes": info["matvec_bytes"],
+                 "achieved_GBs": info["matvec_bytes"] / (el / args.steps) / 1e9,
+                 "frac_hbm_peak": info["matvec_bytes"] / (el / args.steps) / 1e9 / HBM_PEAK_GBS,
+                 "phase_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+                 "build_s": build_s, "device_bytes": info["bytes_total"],
+                 "n_adm": info["n_adm"], "n_near": info["n_near"], "near_entries": info["near_entries"],
+                 "nclusters": info["nclusters"]},
+    }
+    A.close()
+    del A
+    torch.cuda.empty_cache()
+    if not args.no_fp64 and storage != "f64":
+        log("bench: FP64-storage comparison")
+        B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage="f64")
+        y64 = torch.zeros_like(x)
+        el64, prof64 = measure(B, x, y64, max(3, args.steps // 2), 1, torch, h2)
+        st64 = max(3, args.steps // 2)
+        out["fp64_compare"] = {"value": st64 / el64, "unit": "matvec/s",
+                               "algorithmic_bytes": B.info["matvec_bytes"],
+                               "frac_hbm_peak": B.info["matvec_bytes"] / (el64 / st64) / 1e9 / HBM_PEAK_GBS,
+                               "speedup_f32_over_f64": (args.steps / el) / (st64 / el64)}
+        B.close()
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle sample")
+        try:
+            out["cpu_baseline"] = cpu_baseline_sample(kind, level, order, leaf, seed)
+        except Exception as e:  # the baseline is a report, never a reason to lose the line
+            out["cpu_baseline"] = {"value": None, "error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

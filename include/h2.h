@@ -1,0 +1,191 @@
+/*
+ * h2.h -- C ABI of the MI355X H^2-matrix library.
+ *
+ * The library builds and applies the interpolation-based H^2 approximation
+ * G~ of the Galerkin matrix G of a boundary integral operator (Boerm,
+ * "Distributed H^2-matrices for boundary element methods"):
+ *
+ *   g_ij = int_{T_i} int_{T_j} g(x, y) dy dx      (Introduction, def. of g_ij)
+ *
+ * with piecewise-constant test and trial functions phi_i = psi_i = indicator
+ * of triangle T_i, the Laplace kernel g = 1/(4 pi |x-y|) or the Helmholtz
+ * kernel g = exp(i kappa |x-y|)/(4 pi |x-y|) (Introduction).  G~ consists of
+ * (Section "H^2-matrices"):
+ *   - a cluster tree (Definition 1) built by bisection of triangle centroids,
+ *     clusters being minimal axis-parallel boxes containing their triangles;
+ *   - a block tree whose admissible leaves satisfy
+ *     max(diam tau, diam sigma) <= 2 eta dist(tau, sigma)  (eq. admissibility);
+ *   - leaf matrices V_tau (eq. leafV), transfer matrices E_tau (eq. transfer)
+ *     and coupling matrices S_{tau sigma} (eq. coupling) from tensor Chebyshev
+ *     interpolation of order m (k = m^3 points per cluster);
+ *   - dense near-field blocks for the inadmissible leaves, evaluated with
+ *     Radon's 7-point rule per triangle, or Sauter-Schwab quadrature of order
+ *     q_ss for triangles that share a vertex (Section "Distributed H^2-matrices",
+ *     experiments: Sauter-Schwab quadrature).
+ * The product y <- y + alpha G~ x is evaluated on the GPU by the three phases of
+ * the paper's matrix-vector multiplication: forward transformation (Algorithm 1),
+ * interaction phase (Algorithm 3) and backward transformation (Algorithm 2).
+ *
+ * Conventions for every entry point:
+ *   - Return value: H2_OK (0) on success, a negative H2_E* code on failure;
+ *     h2_last_error() then returns a thread-local message.  No C++ exception
+ *     crosses this interface.  A failed call leaves a valid handle valid.
+ *   - Vectors x, y, b, z are DEVICE pointers owned by the caller, column-major
+ *     n x nrhs with leading dimension ld >= n, in the ORIGINAL triangle order.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Matrix
+ *     products are asynchronous on that stream; h2_solve returns when done.
+ *   - Mesh arrays are HOST pointers, copied by build_h2; the caller keeps them.
+ *   - The handle owns all device memory of the matrix; h2_free releases it.
+ *   - Calls on one handle must not overlap in time (one handle, one stream at a
+ *     time); different handles are independent.
+ */
+#ifndef H2_MI355X_H
+#define H2_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define H2_OK 0
+#define H2_EINVAL (-1)    /* invalid argument */
+#define H2_ENOMEM (-2)    /* device or host allocation failed */
+#define H2_EHIP (-3)      /* HIP runtime error */
+#define H2_ENOTCONV (-4)  /* solver did not reach the tolerance (outputs still written) */
+#define H2_EINTERNAL (-5) /* unexpected internal error */
+
+/* kernel functions g(x, y) */
+#define H2_LAPLACE 0        /* 1/(4 pi |x-y|) */
+#define H2_HELMHOLTZ 1      /* exp(i kappa |x-y|)/(4 pi |x-y|), complex matrix */
+#define H2_TEST_ONE 2       /* g = 1; closed-form test kernel */
+#define H2_TEST_BILINEAR 3  /* g = x.y; closed-form test kernel */
+#define H2_TEST_QUADRATIC 4 /* g = (x.y)^2; closed-form test kernel */
+
+/* storage precision of V, E, S and the near field */
+#define H2_F64 0       /* everything FP64 */
+#define H2_F32 1       /* everything FP32 */
+#define H2_F32_SBF16 2 /* coupling matrices BF16, the rest FP32 */
+
+/* element type of user vectors */
+#define H2_R64 0 /* double */
+#define H2_R32 1 /* float */
+
+/* h2_matvec flags */
+#define H2_ACC_F64 1 /* accumulate in FP64 even when the matrix is stored in FP32/BF16 */
+
+/* h2_params.flags */
+#define H2_HOST_ONLY 1 /* build only the trees (no device work); for structure inspection */
+
+typedef struct h2_handle_s* h2_handle;
+
+typedef struct {
+  int64_t nv;               /* number of vertices */
+  int64_t nt;               /* number of triangles = n */
+  const double* vertices;   /* nv x 3, row-major, host */
+  const int32_t* triangles; /* nt x 3 vertex indices, row-major, host */
+} h2_mesh;
+
+typedef struct {
+  int kernel;     /* H2_LAPLACE, ...                                          */
+  double kappa;   /* Helmholtz wave number (ignored otherwise)                */
+  int order_m;    /* interpolation points per axis, 1..6; k = m^3             */
+  int leaf_size;  /* clusters with more triangles are split                   */
+  double eta;     /* admissibility parameter of eq. admissibility             */
+  int q_ss;       /* Gauss-Legendre order per axis of the Sauter-Schwab rules */
+  int storage;    /* H2_F64, H2_F32, H2_F32_SBF16                             */
+  int flags;      /* H2_HOST_ONLY or 0                                        */
+} h2_params;
+
+typedef struct {
+  int64_t n, nclusters, nleaves, depth, n_adm, n_near, near_entries;
+  int64_t m, k, storage, kernel;
+  int64_t bytes_S, bytes_N, bytes_V, bytes_E, bytes_total; /* device storage */
+  double matvec_bytes; /* algorithmic HBM bytes of one single-vector product:
+                          V twice, E twice, S once, near field once */
+  double matvec_flops; /* 2 flops per stored scalar used (x4 for complex)    */
+} h2_stats;
+
+/* Builds the H^2 matrix of the mesh (trees on the host, all matrix entries on
+ * the current HIP device).  *out receives a new handle on success. */
+int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out);
+
+/* y <- y + alpha G~ x for nrhs columns.  dtype: H2_R64 or H2_R32 for x and y.
+ * flags: 0 or H2_ACC_F64.  Asynchronous on `stream`. */
+int h2_matvec(h2_handle h, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
+              double alpha, int flags, void* stream);
+
+/* Solver for G~ z = b (Introduction: Krylov methods). */
+#define H2_CG 0
+#define H2_GMRES 1
+typedef struct {
+  int method;        /* H2_CG (Laplace: G~ symmetric positive definite) or H2_GMRES */
+  int restart;       /* GMRES restart length                                         */
+  int maxit;         /* maximum number of inner iterations in total                 */
+  double rtol;       /* stop when ||b - G~ z|| <= rtol ||b||                        */
+  int refine;        /* 0: plain solve with the matrix's own accumulation;
+                        1: FP64 iterative refinement -- outer residuals with FP64
+                           accumulation, inner solves with storage-precision
+                           accumulation to inner_rtol                              */
+  double inner_rtol; /* inner tolerance of the refinement                          */
+} h2_solve_params;
+
+typedef struct {
+  int iterations;       /* total inner iterations                          */
+  int outer;            /* refinement steps (1 without refinement)         */
+  double rel_residual;  /* ||b - G~ z|| / ||b|| recomputed at the end, FP64 */
+  double seconds;       /* wall time                                        */
+} h2_solve_info;
+
+/* Solves G~ z = b for one right-hand side (x and b FP64, device).  z is both
+ * the initial guess and the result.  Returns H2_ENOTCONV if rtol was not met. */
+int h2_solve(h2_handle h, const double* b, double* z, const h2_solve_params* p,
+             h2_solve_info* info, void* stream);
+
+int h2_info(h2_handle h, h2_stats* out);
+void h2_free(h2_handle h);
+const char* h2_last_error(void);
+
+/* Structure and data export for inspection and tests (host copies).
+ * what: H2_X_PERM      int32[n]           position -> triangle
+ *       H2_X_CLUSTERS  int32[nclusters*6] begin, end, parent, child0, child1, level
+ *       H2_X_BOXES     double[nclusters*6] lo xyz, hi xyz
+ *       H2_X_ADM       int32[n_adm*2]     (row cluster, column cluster)
+ *       H2_X_NEAR      int32[n_near*2]    (row cluster, column cluster)
+ *       H2_X_DFS       int32[nclusters]   depth-first pre-order number
+ *       H2_X_V         double[|tau| * k]  leaf matrix of cluster `index` (row-major)
+ *       H2_X_E         double[k * k]      transfer matrix of cluster `index` (row nu')
+ *       H2_X_S         double[k * k]      coupling matrix of admissible block `index`
+ *       H2_X_N         double[|tau|*|sigma|] near block `index` (row-major)
+ * For complex kernels H2_X_S and H2_X_N return interleaved (re, im) pairs.
+ * `cap` is the capacity of dst in elements; H2_EINVAL if too small. */
+#define H2_X_PERM 0
+#define H2_X_CLUSTERS 1
+#define H2_X_BOXES 2
+#define H2_X_ADM 3
+#define H2_X_NEAR 4
+#define H2_X_DFS 5
+#define H2_X_V 6
+#define H2_X_E 7
+#define H2_X_S 8
+#define H2_X_N 9
+int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap);
+
+/* Per-phase device timing of h2_matvec (HIP events on the call's stream).
+ * h2_profile(h, 1) enables and clears; h2_profile(h, 0) disables.
+ * h2_profile_read fills ms[H2_NPHASE] with summed milliseconds and
+ * calls[H2_NPHASE] with launch counts since the last clear (synchronizes). */
+#define H2_PH_FORWARD 0  /* permute-in, leaf forward, transfer up        */
+#define H2_PH_COUPLING 1 /* coupling S x-hat                              */
+#define H2_PH_DOWN 2     /* transfer down                                 */
+#define H2_PH_NEAR 3     /* near field + leaf backward (+ permute-out)    */
+#define H2_PH_TOTAL 4    /* the whole product                              */
+#define H2_NPHASE 5
+int h2_profile(h2_handle h, int enable);
+int h2_profile_read(h2_handle h, double* ms, int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2_MI355X_H */

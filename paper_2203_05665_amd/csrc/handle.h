@@ -1,0 +1,96 @@
+// Internal state of an h2_handle: host structure, device arrays, workspaces.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/h2.h"
+#include "structure.h"
+
+namespace h2 {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define H2_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw ::h2::Error(e_ == hipErrorOutOfMemory ? H2_ENOMEM : H2_EHIP,                    \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+// Owning device allocation.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 16;
+    H2_HIP(hipMalloc(&p, b));
+    bytes = b;
+  }
+  template <class T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) H2_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// bf16 storage element (upper half of an IEEE float).
+struct bf16 {
+  uint16_t v;
+};
+
+}  // namespace h2
+
+struct h2_handle_s {
+  h2::Structure S;
+  h2_params P{};
+  bool host_only = false;
+  bool is_complex = false;
+  int device = 0;
+  size_t val_bytes = 8;   // bytes per stored real scalar of V, E, N
+  size_t s_bytes = 8;     // bytes per stored real scalar of S
+  // device structure
+  h2::DBuf perm, cbegin, cend, parent, child0, child1, leaves, adm_ptr, adm_col, near_ptr, near_col,
+      panel_off, up_list, pts;
+  std::vector<int64_t> up_ptr;  // host offsets into up_list per level
+  // matrix data
+  h2::DBuf Vf, Vb, F, ET, Smat, Nmat;
+  // workspaces (sized for FP64 vectors, one right-hand side)
+  h2::DBuf xc, yc, xhat, yhat;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> events;     // pool
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[H2_NPHASE] = {0};
+  int64_t calls[H2_NPHASE] = {0};
+  ~h2_handle_s();
+};
+
+namespace h2 {
+void assemble(h2_handle_s& H);  // fills Vf, Vb, F, ET, Smat, Nmat on the device
+void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
+            double alpha, int flags, hipStream_t s);
+int solve(h2_handle_s& H, const double* b, double* z, const h2_solve_params& p, h2_solve_info& info,
+          hipStream_t s);
+hipEvent_t prof_event(h2_handle_s& H);
+void prof_record(h2_handle_s& H, int phase, hipEvent_t a, hipEvent_t b);
+}  // namespace h2

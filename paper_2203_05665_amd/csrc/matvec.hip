@@ -1,0 +1,394 @@
+// The H^2 matrix-vector product y <- y + alpha G~ x on the GPU.
+//
+// Phases (Section "H^2-matrices", three-phase product; Algorithms 1-3):
+//   permute-in      x_c[p] = x[perm[p]]  (each cluster is a contiguous range)
+//   leaf forward    x^_sigma = V_sigma^T x|sigma for every leaf        (Alg. 1)
+//   transfer up     x^_sigma = sum_children F_sigma'^T x^_sigma', level by level,
+//                   deepest first                                      (Alg. 1)
+//   coupling        y^_tau = sum_{(tau,sigma) admissible} S x^_sigma    (Alg. 3)
+//                   (assigns, so y^ := 0 is part of this phase)
+//   transfer down   y^_tau' += E_tau' y^_tau, level by level, root first (Alg. 2)
+//   near + backward y_c|tau = sum_{(tau,sigma) inadmissible} G|tau x sigma x|sigma
+//                   + V_tau y^_tau for every leaf                   (Alg. 3 and 2)
+//   permute-out     y[perm[p]] += alpha y_c[p]
+// Every output element is written by exactly one thread: no atomics, and the
+// result is bitwise reproducible from call to call.
+//
+// Layouts: S blocks k x k row-major, CSR by row cluster; F (= E) row nu' and
+// its transpose ET per cluster; Vf = V row-major [position][nu]; Vb = V per leaf
+// column-major [nu][row]; the near field of row leaf tau is one column-major
+// panel |tau| x (sum |sigma|), blocks in column-cluster order.
+#include <hip/hip_runtime.h>
+
+#include "handle.h"
+
+namespace h2 {
+namespace {
+
+// ---------------------------------------------------------------- element access
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+template <typename ST, typename AT>
+__device__ inline AT ld(const ST* p);
+template <>
+__device__ inline double ld<double, double>(const double* p) { return *p; }
+template <>
+__device__ inline float ld<float, float>(const float* p) { return *p; }
+template <>
+__device__ inline double ld<float, double>(const float* p) { return static_cast<double>(*p); }
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+// 16-byte vector of storage elements converted to AT (non-temporal: streamed once)
+template <typename ST>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  static constexpr int N = 2;
+  template <typename AT>
+  __device__ static inline void load(const double* p, AT* out) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    out[0] = v.x;
+    out[1] = v.y;
+  }
+};
+template <>
+struct Vec16<float> {
+  static constexpr int N = 4;
+  template <typename AT>
+  __device__ static inline void load(const float* p, AT* out) {
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  }
+};
+template <>
+struct Vec16<bf16> {
+  static constexpr int N = 8;
+  template <typename AT>
+  __device__ static inline void load(const bf16* p, AT* out) {
+    const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p));
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      out[2 * i] = __uint_as_float(w[i] << 16);
+      out[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+};
+
+// ---------------------------------------------------------------- permutations
+template <typename XT, typename AT>
+__global__ void permute_in(int64_t n, const int32_t* __restrict__ perm, const XT* __restrict__ x,
+                           AT* __restrict__ xc) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) xc[p] = static_cast<AT>(x[perm[p]]);
+}
+
+template <typename XT, typename AT>
+__global__ void permute_out(int64_t n, const int32_t* __restrict__ perm, const AT* __restrict__ yc, XT* __restrict__ y,
+                            double alpha) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) {
+    const int32_t t = perm[p];
+    y[t] = static_cast<XT>(static_cast<double>(y[t]) + alpha * static_cast<double>(yc[p]));
+  }
+}
+
+// ---------------------------------------------------------------- leaf forward
+// one wave per leaf, lane = nu (loops for k > 64)
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void leaf_forward(int nleaves, int k, const int32_t* __restrict__ leaves,
+                                                    const int32_t* __restrict__ cbegin,
+                                                    const int32_t* __restrict__ cend, const ST* __restrict__ Vf,
+                                                    const AT* __restrict__ xc, AT* __restrict__ xhat) {
+  const int l = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (l >= nleaves) return;
+  const int32_t c = leaves[l];
+  const int64_t b0 = cbegin[c], e0 = cend[c];
+  for (int nu = lane; nu < k; nu += 64) {
+    AT acc = 0;
+    for (int64_t p = b0; p < e0; ++p) acc += ld<ST, AT>(Vf + p * k + nu) * xc[p];
+    xhat[static_cast<int64_t>(c) * k + nu] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- transfers
+// up: one wave per non-leaf cluster of a level; lane = parent index nu
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void transfer_up(int count, int k, const int32_t* __restrict__ list,
+                                                   const int32_t* __restrict__ child0,
+                                                   const int32_t* __restrict__ child1, const ST* __restrict__ F,
+                                                   AT* __restrict__ xhat) {
+  const int w = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (w >= count) return;
+  const int32_t c = list[w];
+  const int32_t ch[2] = {child0[c], child1[c]};
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  for (int nu = lane; nu < k; nu += 64) {
+    AT acc = 0;
+    for (int a = 0; a < 2; ++a) {
+      const ST* Fc = F + ch[a] * kk;
+      const AT* xs = xhat + static_cast<int64_t>(ch[a]) * k;
+      for (int nup = 0; nup < k; ++nup) acc += ld<ST, AT>(Fc + static_cast<int64_t>(nup) * k + nu) * xs[nup];
+    }
+    xhat[static_cast<int64_t>(c) * k + nu] = acc;
+  }
+}
+
+// down: one wave per cluster of a level (all have parents); lane = child index nu'
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void transfer_down(int first, int count, int k, const int32_t* __restrict__ parent,
+                                                     const ST* __restrict__ ET, AT* __restrict__ yhat) {
+  const int w = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (w >= count) return;
+  const int32_t c = first + w;
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  const ST* Ec = ET + c * kk;
+  const AT* yp = yhat + static_cast<int64_t>(parent[c]) * k;
+  for (int nup = lane; nup < k; nup += 64) {
+    AT acc = 0;
+    for (int nu = 0; nu < k; ++nu) acc += ld<ST, AT>(Ec + static_cast<int64_t>(nu) * k + nup) * yp[nu];
+    yhat[static_cast<int64_t>(c) * k + nup] += acc;
+  }
+}
+
+// ---------------------------------------------------------------- coupling
+// k = 64 fast path: one 256-thread workgroup per row cluster; each thread reads
+// 16-byte vectors of S (lanes_per_row lanes cover one row of a block) and keeps
+// its partial row sums in registers across all blocks of the row; one shuffle
+// reduction at the end.
+template <typename SST, typename AT>
+__global__ __launch_bounds__(256) void coupling64(int nc, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const SST* __restrict__ S,
+                                                  const AT* __restrict__ xhat, AT* __restrict__ yhat) {
+  constexpr int VEC = Vec16<SST>::N;
+  constexpr int LPR = 64 / VEC;
+  constexpr int RPP = 256 / LPR;
+  constexpr int NP = 64 / RPP;
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int t = threadIdx.x;
+  const int lr = t % LPR, r0 = t / LPR;
+  AT acc[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) acc[j] = 0;
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau]; b < b1; ++b) {
+    const int64_t s = col[b];
+    AT xv[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) xv[v] = xhat[s * 64 + lr * VEC + v];
+    const SST* Sb = S + b * 4096 + lr * VEC;
+    AT sv[NP][VEC];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) Vec16<SST>::load(Sb + (r0 + j * RPP) * 64, sv[j]);
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[j] += sv[j][v] * xv[v];
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+  if (lr == 0) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) yhat[static_cast<int64_t>(tau) * 64 + r0 + j * RPP] = acc[j];
+  }
+}
+
+// any k: one thread per row nu of the block row
+template <typename SST, typename AT>
+__device__ inline AT lds(const SST* p);
+template <>
+__device__ inline double lds<double, double>(const double* p) { return *p; }
+template <>
+__device__ inline float lds<float, float>(const float* p) { return *p; }
+template <>
+__device__ inline double lds<float, double>(const float* p) { return *p; }
+template <>
+__device__ inline float lds<bf16, float>(const bf16* p) { return bf2f(p->v); }
+template <>
+__device__ inline double lds<bf16, double>(const bf16* p) { return bf2f(p->v); }
+
+template <typename SST, typename AT>
+__global__ __launch_bounds__(256) void coupling_any(int nc, int k, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col, const SST* __restrict__ S,
+                                                   const AT* __restrict__ xhat, AT* __restrict__ yhat) {
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  for (int nu = threadIdx.x; nu < k; nu += blockDim.x) {
+    AT acc = 0;
+    for (int64_t b = ptr[tau]; b < ptr[tau + 1]; ++b) {
+      const SST* Sb = S + b * kk + static_cast<int64_t>(nu) * k;
+      const AT* xs = xhat + static_cast<int64_t>(col[b]) * k;
+      for (int mu = 0; mu < k; ++mu) acc += lds<SST, AT>(Sb + mu) * xs[mu];
+    }
+    yhat[static_cast<int64_t>(tau) * k + nu] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- near field + leaf backward
+// one 256-thread workgroup per row leaf; lane = row of the leaf, the four waves
+// take every fourth column of the panel; LDS sums the four partial results.
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const int32_t* __restrict__ leaves,
+                                                     const int32_t* __restrict__ cbegin,
+                                                     const int32_t* __restrict__ cend,
+                                                     const int64_t* __restrict__ near_ptr,
+                                                     const int32_t* __restrict__ near_col,
+                                                     const int64_t* __restrict__ panel_off,
+                                                     const ST* __restrict__ N, const ST* __restrict__ Vb,
+                                                     const AT* __restrict__ xc, const AT* __restrict__ yhat,
+                                                     AT* __restrict__ yc) {
+  __shared__ AT part[4][64];
+  const int l = blockIdx.x;
+  if (l >= nleaves) return;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int32_t tau = leaves[l];
+  const int64_t b0 = cbegin[tau], r = cend[tau] - b0;
+  const ST* P = N + panel_off[l];
+  const ST* Vl = Vb + b0 * k;
+  const AT* yh = yhat + static_cast<int64_t>(tau) * k;
+  for (int64_t i0 = 0; i0 < r; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const bool on = i < r;
+    AT acc = 0;
+    int64_t colbase = 0;
+    for (int64_t bb = near_ptr[l]; bb < near_ptr[l + 1]; ++bb) {
+      const int32_t s = near_col[bb];
+      const int64_t s0 = cbegin[s], w = cend[s] - s0;
+      if (on) {
+        const ST* Pc = P + colbase * r + i;
+        for (int64_t j = wave; j < w; j += 4) acc += ld<ST, AT>(Pc + j * r) * xc[s0 + j];
+      }
+      colbase += w;
+    }
+    if (on)
+      for (int nu = wave; nu < k; nu += 4) acc += ld<ST, AT>(Vl + static_cast<int64_t>(nu) * r + i) * yh[nu];
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && on) yc[b0 + i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    __syncthreads();
+  }
+}
+
+inline unsigned blocks_for(int64_t work, int per) {
+  const int64_t g = (work + per - 1) / per;
+  if (g > 0x7fffffff) throw Error(H2_EINVAL, "launch too large");
+  return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+template <typename SST, typename ST, typename AT, typename XT>
+void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t st) {
+  const Structure& S = H.S;
+  const int k = S.k;
+  const int64_t n = S.n;
+  const int nc = S.nclusters;
+  const int nl = static_cast<int>(S.leaves.size());
+  AT* xc = H.xc.as<AT>();
+  AT* yc = H.yc.as<AT>();
+  AT* xh = H.xhat.as<AT>();
+  AT* yh = H.yhat.as<AT>();
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+  if (H.prof) {
+    e0 = prof_event(H);
+    H2_HIP(hipEventRecord(e0, st));
+  }
+  permute_in<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), x, xc);
+  leaf_forward<ST, AT><<<blocks_for(nl, 4), 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                           H.cend.as<int32_t>(), H.Vf.as<ST>(), xc, xh);
+  for (int l = S.depth - 1; l >= 0; --l) {
+    const int cnt = static_cast<int>(H.up_ptr[l + 1] - H.up_ptr[l]);
+    if (cnt == 0) continue;
+    transfer_up<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, k, H.up_list.as<int32_t>() + H.up_ptr[l],
+                                                             H.child0.as<int32_t>(), H.child1.as<int32_t>(),
+                                                             H.F.as<ST>(), xh);
+  }
+  if (H.prof) {
+    e1 = prof_event(H);
+    H2_HIP(hipEventRecord(e1, st));
+  }
+  if (k == 64)
+    coupling64<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<SST>(),
+                                           xh, yh);
+  else
+    coupling_any<SST, AT><<<nc, 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
+                                             H.Smat.as<SST>(), xh, yh);
+  if (H.prof) {
+    e2 = prof_event(H);
+    H2_HIP(hipEventRecord(e2, st));
+  }
+  for (int l = 0; l < S.depth; ++l) {
+    const int first = S.level_ptr[l + 1], cnt = S.level_ptr[l + 2] - S.level_ptr[l + 1];
+    if (cnt == 0) continue;
+    transfer_down<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, k, H.parent.as<int32_t>(), H.ET.as<ST>(),
+                                                               yh);
+  }
+  if (H.prof) {
+    e3 = prof_event(H);
+    H2_HIP(hipEventRecord(e3, st));
+  }
+  near_backward<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                            H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                            H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
+                                            H.Vb.as<ST>(), xc, yh, yc);
+  permute_out<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), yc, y, alpha);
+  H2_HIP(hipGetLastError());
+  if (H.prof) {
+    e4 = prof_event(H);
+    H2_HIP(hipEventRecord(e4, st));
+    prof_record(H, H2_PH_FORWARD, e0, e1);
+    prof_record(H, H2_PH_COUPLING, e1, e2);
+    prof_record(H, H2_PH_DOWN, e2, e3);
+    prof_record(H, H2_PH_NEAR, e3, e4);
+    prof_record(H, H2_PH_TOTAL, e0, e4);
+  }
+}
+
+template <typename SST, typename ST, typename AT>
+void matvec_x(h2_handle_s& H, int dtype, const void* x, void* y, double alpha, hipStream_t st) {
+  if (dtype == H2_R64)
+    matvec_typed<SST, ST, AT, double>(H, static_cast<const double*>(x), static_cast<double*>(y), alpha, st);
+  else
+    matvec_typed<SST, ST, AT, float>(H, static_cast<const float*>(x), static_cast<float*>(y), alpha, st);
+}
+
+}  // namespace
+
+void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy, double alpha,
+            int flags, hipStream_t st) {
+  if (H.host_only) throw Error(H2_EINVAL, "handle was built with H2_HOST_ONLY");
+  if (H.is_complex) throw Error(H2_EINVAL, "complex kernels are applied with h2_matvec_complex");
+  if (nrhs < 0) throw Error(H2_EINVAL, "nrhs must be >= 0");
+  if (dtype != H2_R64 && dtype != H2_R32) throw Error(H2_EINVAL, "dtype must be H2_R64 or H2_R32");
+  if (nrhs > 0 && (x == nullptr || y == nullptr)) throw Error(H2_EINVAL, "x and y must not be NULL");
+  if (ldx < H.S.n || ldy < H.S.n) throw Error(H2_EINVAL, "leading dimension smaller than n");
+  const size_t es = dtype == H2_R64 ? 8 : 4;
+  const bool acc64 = (flags & H2_ACC_F64) != 0;
+  for (int j = 0; j < nrhs; ++j) {
+    const void* xj = static_cast<const char*>(x) + static_cast<size_t>(j) * ldx * es;
+    void* yj = static_cast<char*>(y) + static_cast<size_t>(j) * ldy * es;
+    switch (H.P.storage) {
+      case H2_F64: matvec_x<double, double, double>(H, dtype, xj, yj, alpha, st); break;
+      case H2_F32:
+        if (acc64) matvec_x<float, float, double>(H, dtype, xj, yj, alpha, st);
+        else matvec_x<float, float, float>(H, dtype, xj, yj, alpha, st);
+        break;
+      default:
+        if (acc64) matvec_x<bf16, float, double>(H, dtype, xj, yj, alpha, st);
+        else matvec_x<bf16, float, float>(H, dtype, xj, yj, alpha, st);
+    }
+  }
+}
+
+}  // namespace h2

@@ -1,0 +1,245 @@
+// Cluster tree and block tree construction on the host (see structure.h).
+// Compiled with -ffp-contract=off: every comparison that decides the tree or
+// the block partition is evaluated in plain IEEE double arithmetic.
+#include "structure.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+
+namespace h2 {
+namespace {
+
+struct Node {
+  int32_t begin, end, level, parent, child[2];
+  double lo[3], hi[3];
+};
+
+struct TreeBuilder {
+  const double* V;
+  const int32_t* T;
+  int leaf;
+  std::vector<int32_t> idx, tmp;
+  std::vector<double> cen;  // n x 3
+  std::vector<Node> nodes;  // depth-first pre-order
+
+  int32_t build(int32_t begin, int32_t end, int32_t level, int32_t parent) {
+    const int32_t id = static_cast<int32_t>(nodes.size());
+    nodes.push_back(Node{begin, end, level, parent, {-1, -1}, {0, 0, 0}, {0, 0, 0}});
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t p = begin; p < end; ++p) {
+      const int32_t t = idx[p];
+      for (int a = 0; a < 3; ++a) {
+        const double* v = V + 3 * static_cast<int64_t>(T[3 * static_cast<int64_t>(t) + a]);
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = std::min(lo[d], v[d]);
+          hi[d] = std::max(hi[d], v[d]);
+        }
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      nodes[id].lo[d] = lo[d];
+      nodes[id].hi[d] = hi[d];
+    }
+    const int32_t size = end - begin;
+    if (size <= leaf) return id;
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t p = begin; p < end; ++p) {
+      const double* c = &cen[3 * static_cast<int64_t>(idx[p])];
+      for (int d = 0; d < 3; ++d) {
+        clo[d] = std::min(clo[d], c[d]);
+        chi[d] = std::max(chi[d], c[d]);
+      }
+    }
+    int axis = 0;
+    double ext[3] = {chi[0] - clo[0], chi[1] - clo[1], chi[2] - clo[2]};
+    for (int d = 1; d < 3; ++d)
+      if (ext[d] > ext[axis]) axis = d;
+    if (!(ext[axis] > 0.0)) return id;
+    const double mid = 0.5 * (clo[axis] + chi[axis]);
+    int32_t nlow = 0;
+    for (int32_t p = begin; p < end; ++p)
+      if (cen[3 * static_cast<int64_t>(idx[p]) + axis] < mid) ++nlow;
+    if (nlow == 0 || nlow == size) return id;
+    // stable partition: low side first, both sides keep their relative order
+    int32_t a = begin, b = begin + nlow;
+    for (int32_t p = begin; p < end; ++p) {
+      const int32_t t = idx[p];
+      if (cen[3 * static_cast<int64_t>(t) + axis] < mid) tmp[a++] = t; else tmp[b++] = t;
+    }
+    std::copy(tmp.begin() + begin, tmp.begin() + end, idx.begin() + begin);
+    const int32_t c0 = build(begin, begin + nlow, level + 1, id);
+    const int32_t c1 = build(begin + nlow, end, level + 1, id);
+    nodes[id].child[0] = c0;
+    nodes[id].child[1] = c1;
+    return id;
+  }
+};
+
+inline double diam(const Structure& S, int32_t c) {
+  const double d0 = S.hi[3 * c] - S.lo[3 * c];
+  const double d1 = S.hi[3 * c + 1] - S.lo[3 * c + 1];
+  const double d2 = S.hi[3 * c + 2] - S.lo[3 * c + 2];
+  return std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+inline double dist(const Structure& S, int32_t t, int32_t s) {
+  double g[3];
+  for (int d = 0; d < 3; ++d) {
+    const double a = S.lo[3 * s + d] - S.hi[3 * t + d];
+    const double b = S.lo[3 * t + d] - S.hi[3 * s + d];
+    g[d] = std::max(0.0, std::max(a, b));
+  }
+  return std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+}
+
+struct BlockBuilder {
+  const Structure& S;
+  std::vector<double> dia;
+  std::vector<std::pair<int32_t, int32_t>> adm, near;
+  explicit BlockBuilder(const Structure& s) : S(s) {
+    dia.resize(S.nclusters);
+    for (int32_t c = 0; c < S.nclusters; ++c) dia[c] = diam(S, c);
+  }
+  void visit(int32_t t, int32_t s) {
+    const double lhs = std::max(dia[t], dia[s]);
+    if (lhs <= 2.0 * S.eta * dist(S, t, s)) {
+      adm.emplace_back(t, s);
+      return;
+    }
+    const bool ct = S.child0[t] >= 0, cs = S.child0[s] >= 0;
+    if (ct && cs) {
+      visit(S.child0[t], S.child0[s]);
+      visit(S.child0[t], S.child1[s]);
+      visit(S.child1[t], S.child0[s]);
+      visit(S.child1[t], S.child1[s]);
+    } else if (cs) {
+      visit(t, S.child0[s]);
+      visit(t, S.child1[s]);
+    } else if (ct) {
+      visit(S.child0[t], s);
+      visit(S.child1[t], s);
+    } else {
+      near.emplace_back(t, s);
+    }
+  }
+};
+
+}  // namespace
+
+void build_structure(Structure& S, const double* vertices, int64_t nv, const int32_t* triangles,
+                     int64_t nt, int m, int leaf_size, double eta) {
+  if (nt <= 0 || nv <= 0) throw std::runtime_error("empty mesh");
+  if (nt > (int64_t(1) << 30)) throw std::runtime_error("too many triangles");
+  if (m < 1 || m > 6) throw std::runtime_error("order m must be in [1, 6]");
+  if (leaf_size < 1) throw std::runtime_error("leaf_size must be >= 1");
+  if (!(eta > 0.0)) throw std::runtime_error("eta must be > 0");
+  for (int64_t i = 0; i < 3 * nt; ++i)
+    if (triangles[i] < 0 || triangles[i] >= nv) throw std::runtime_error("triangle vertex index out of range");
+  S = Structure();
+  S.n = nt;
+  S.m = m;
+  S.k = m * m * m;
+  S.leaf_size = leaf_size;
+  S.eta = eta;
+  S.vert.assign(vertices, vertices + 3 * nv);
+  S.tri.assign(triangles, triangles + 3 * nt);
+
+  TreeBuilder tb{S.vert.data(), S.tri.data(), leaf_size, {}, {}, {}, {}};
+  tb.idx.resize(nt);
+  tb.tmp.resize(nt);
+  std::iota(tb.idx.begin(), tb.idx.end(), 0);
+  tb.cen.resize(3 * nt);
+  for (int64_t t = 0; t < nt; ++t) {
+    const double* p0 = &S.vert[3 * static_cast<int64_t>(S.tri[3 * t])];
+    const double* p1 = &S.vert[3 * static_cast<int64_t>(S.tri[3 * t + 1])];
+    const double* p2 = &S.vert[3 * static_cast<int64_t>(S.tri[3 * t + 2])];
+    for (int d = 0; d < 3; ++d) tb.cen[3 * t + d] = (p0[d] + p1[d] + p2[d]) / 3.0;
+  }
+  tb.build(0, static_cast<int32_t>(nt), 0, -1);
+  S.perm = tb.idx;
+
+  // renumber breadth first (stable within a level = depth-first order)
+  const int32_t nc = static_cast<int32_t>(tb.nodes.size());
+  S.nclusters = nc;
+  int32_t depth = 0;
+  for (const Node& nd : tb.nodes) depth = std::max(depth, nd.level);
+  S.depth = depth;
+  std::vector<int32_t> order(nc);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return tb.nodes[a].level < tb.nodes[b].level; });
+  std::vector<int32_t> newid(nc);
+  for (int32_t i = 0; i < nc; ++i) newid[order[i]] = i;
+  S.cbegin.resize(nc); S.cend.resize(nc); S.parent.resize(nc); S.child0.resize(nc);
+  S.child1.resize(nc); S.level.resize(nc); S.dfs_id.resize(nc);
+  S.lo.resize(3 * nc); S.hi.resize(3 * nc);
+  S.level_ptr.assign(depth + 2, 0);
+  for (int32_t i = 0; i < nc; ++i) {
+    const Node& nd = tb.nodes[order[i]];
+    S.cbegin[i] = nd.begin;
+    S.cend[i] = nd.end;
+    S.parent[i] = nd.parent >= 0 ? newid[nd.parent] : -1;
+    S.child0[i] = nd.child[0] >= 0 ? newid[nd.child[0]] : -1;
+    S.child1[i] = nd.child[1] >= 0 ? newid[nd.child[1]] : -1;
+    S.level[i] = nd.level;
+    S.dfs_id[i] = order[i];
+    for (int d = 0; d < 3; ++d) {
+      S.lo[3 * i + d] = nd.lo[d];
+      S.hi[3 * i + d] = nd.hi[d];
+    }
+    S.level_ptr[nd.level + 1]++;
+  }
+  for (int l = 0; l <= depth; ++l) S.level_ptr[l + 1] += S.level_ptr[l];
+
+  for (int32_t i = 0; i < nc; ++i)
+    if (S.child0[i] < 0) S.leaves.push_back(i);
+  std::sort(S.leaves.begin(), S.leaves.end(),
+            [&](int32_t a, int32_t b) { return S.cbegin[a] < S.cbegin[b]; });
+  S.leaf_of_pos.resize(nt);
+  for (size_t l = 0; l < S.leaves.size(); ++l)
+    for (int32_t p = S.cbegin[S.leaves[l]]; p < S.cend[S.leaves[l]]; ++p) S.leaf_of_pos[p] = static_cast<int32_t>(l);
+
+  // block tree
+  BlockBuilder bb(S);
+  bb.visit(0, 0);
+  auto by_row = [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+    return a.first != b.first ? a.first < b.first : a.second < b.second;
+  };
+  std::sort(bb.adm.begin(), bb.adm.end(), by_row);
+  S.adm_ptr.assign(nc + 1, 0);
+  S.adm_col.resize(bb.adm.size());
+  for (size_t b = 0; b < bb.adm.size(); ++b) {
+    S.adm_ptr[bb.adm[b].first + 1]++;
+    S.adm_col[b] = bb.adm[b].second;
+  }
+  for (int32_t i = 0; i < nc; ++i) S.adm_ptr[i + 1] += S.adm_ptr[i];
+
+  const int32_t nl = static_cast<int32_t>(S.leaves.size());
+  std::vector<int32_t> leaf_index(nc, -1);
+  for (int32_t l = 0; l < nl; ++l) leaf_index[S.leaves[l]] = l;
+  for (auto& pr : bb.near) pr.first = leaf_index[pr.first];
+  std::sort(bb.near.begin(), bb.near.end(), [&](const auto& a, const auto& b) {
+    return a.first != b.first ? a.first < b.first : S.cbegin[a.second] < S.cbegin[b.second];
+  });
+  S.near_ptr.assign(nl + 1, 0);
+  S.near_col.resize(bb.near.size());
+  for (size_t b = 0; b < bb.near.size(); ++b) {
+    S.near_ptr[bb.near[b].first + 1]++;
+    S.near_col[b] = bb.near[b].second;
+  }
+  for (int32_t l = 0; l < nl; ++l) S.near_ptr[l + 1] += S.near_ptr[l];
+  S.panel_off.assign(nl + 1, 0);
+  for (int32_t l = 0; l < nl; ++l) {
+    const int64_t r = S.cend[S.leaves[l]] - S.cbegin[S.leaves[l]];
+    int64_t cols = 0;
+    for (int64_t b = S.near_ptr[l]; b < S.near_ptr[l + 1]; ++b)
+      cols += S.cend[S.near_col[b]] - S.cbegin[S.near_col[b]];
+    S.panel_off[l + 1] = S.panel_off[l] + r * cols;
+  }
+  S.near_entries = S.panel_off[nl];
+}
+
+}  // namespace h2

@@ -1,0 +1,236 @@
+"""ctypes binding of the C ABI in include/h2.h (argument marshalling only).
+
+Every computation happens in libh2mi355x.so; this module converts arrays to
+pointers and checks return codes.  Device vectors are torch CUDA tensors
+(float64 or float32, contiguous, length n or n x nrhs in Fortran order); the
+stream is torch's current stream unless given.  Loading fails loudly if the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libh2mi355x.so")
+
+# constants of include/h2.h
+H2_OK, H2_EINVAL, H2_ENOMEM, H2_EHIP, H2_ENOTCONV, H2_EINTERNAL = 0, -1, -2, -3, -4, -5
+H2_LAPLACE, H2_HELMHOLTZ, H2_TEST_ONE, H2_TEST_BILINEAR, H2_TEST_QUADRATIC = 0, 1, 2, 3, 4
+H2_F64, H2_F32, H2_F32_SBF16 = 0, 1, 2
+H2_R64, H2_R32 = 0, 1
+H2_ACC_F64 = 1
+H2_HOST_ONLY = 1
+H2_CG, H2_GMRES = 0, 1
+(H2_X_PERM, H2_X_CLUSTERS, H2_X_BOXES, H2_X_ADM, H2_X_NEAR, H2_X_DFS, H2_X_V, H2_X_E, H2_X_S,
+ H2_X_N) = range(10)
+H2_PH_FORWARD, H2_PH_COUPLING, H2_PH_DOWN, H2_PH_NEAR, H2_PH_TOTAL, H2_NPHASE = 0, 1, 2, 3, 4, 5
+
+KERNELS = {"laplace": H2_LAPLACE, "helmholtz": H2_HELMHOLTZ, "one": H2_TEST_ONE,
+           "bilinear": H2_TEST_BILINEAR, "quadratic": H2_TEST_QUADRATIC}
+STORAGE = {"f64": H2_F64, "f32": H2_F32, "f32_sbf16": H2_F32_SBF16}
+
+
+class h2_mesh(C.Structure):
+    _fields_ = [("nv", C.c_int64), ("nt", C.c_int64), ("vertices", C.POINTER(C.c_double)),
+                ("triangles", C.POINTER(C.c_int32))]
+
+
+class h2_params(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("kappa", C.c_double), ("order_m", C.c_int), ("leaf_size", C.c_int),
+                ("eta", C.c_double), ("q_ss", C.c_int), ("storage", C.c_int), ("flags", C.c_int)]
+
+
+class h2_stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in ("n", "nclusters", "nleaves", "depth", "n_adm", "n_near",
+                                         "near_entries", "m", "k", "storage", "kernel", "bytes_S",
+                                         "bytes_N", "bytes_V", "bytes_E", "bytes_total")] + \
+               [("matvec_bytes", C.c_double), ("matvec_flops", C.c_double)]
+
+
+class h2_solve_params(C.Structure):
+    _fields_ = [("method", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double),
+                ("refine", C.c_int), ("inner_rtol", C.c_double)]
+
+
+class h2_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("rel_residual", C.c_double),
+                ("seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() "
+                               "(or python paper_2203_05665_amd/build_lib.py) first" % LIBPATH)
+        L = C.CDLL(LIBPATH)
+        L.build_h2.argtypes = [C.POINTER(h2_mesh), C.POINTER(h2_params), C.POINTER(C.c_void_p)]
+        L.h2_matvec.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                C.c_double, C.c_int, C.c_void_p]
+        L.h2_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(h2_solve_params),
+                               C.POINTER(h2_solve_info), C.c_void_p]
+        L.h2_info.argtypes = [C.c_void_p, C.POINTER(h2_stats)]
+        L.h2_free.argtypes = [C.c_void_p]
+        L.h2_free.restype = None
+        L.h2_last_error.restype = C.c_char_p
+        L.h2_export.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64]
+        L.h2_profile.argtypes = [C.c_void_p, C.c_int]
+        L.h2_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("h2 error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != H2_OK:
+        raise H2Error(rc, h2_last_error())
+    return rc
+
+
+def h2_last_error() -> str:
+    m = lib().h2_last_error()
+    return m.decode() if m else ""
+
+
+def build_h2(vertices, triangles, kernel="laplace", kappa=0.0, order=4, leaf=64, eta=0.5, q_ss=4,
+             storage="f64", host_only=False):
+    """Calls build_h2; returns the raw handle (int)."""
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    T = np.ascontiguousarray(triangles, dtype=np.int32)
+    mesh = h2_mesh(V.shape[0], T.shape[0], V.ctypes.data_as(C.POINTER(C.c_double)),
+                   T.ctypes.data_as(C.POINTER(C.c_int32)))
+    prm = h2_params(KERNELS[kernel] if isinstance(kernel, str) else int(kernel), float(kappa), int(order),
+                    int(leaf), float(eta), int(q_ss), STORAGE[storage] if isinstance(storage, str) else int(storage),
+                    H2_HOST_ONLY if host_only else 0)
+    h = C.c_void_p()
+    _check(lib().build_h2(C.byref(mesh), C.byref(prm), C.byref(h)))
+    return h.value
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
+    """y <- y + alpha G~ x for torch CUDA tensors x, y (n or n x nrhs, Fortran order)."""
+    import torch
+    if x.dtype != y.dtype or x.dtype not in (torch.float64, torch.float32):
+        raise TypeError("x and y must both be float64 or both float32")
+    if not (x.is_cuda and y.is_cuda):
+        raise TypeError("x and y must be device tensors")
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    n = x.shape[0]
+    ldx = x.stride(1) if x.dim() == 2 else n
+    ldy = y.stride(1) if y.dim() == 2 else n
+    if x.stride(0) != 1 or y.stride(0) != 1:
+        raise ValueError("columns must be contiguous")
+    dt = H2_R64 if x.dtype == torch.float64 else H2_R32
+    _check(lib().h2_matvec(h, nrhs, dt, x.data_ptr(), ldx, y.data_ptr(), ldy, float(alpha),
+                           H2_ACC_F64 if acc64 else 0, _stream(stream)))
+    return y
+
+
+def h2_solve(h, b, z, method="cg", rtol=1e-8, maxit=1000, restart=50, refine=False, inner_rtol=1e-4,
+             stream=None, check=True):
+    """Solves G~ z = b (float64 device tensors); z holds the initial guess and the result."""
+    p = h2_solve_params(H2_CG if method == "cg" else H2_GMRES, int(restart), int(maxit), float(rtol),
+                        1 if refine else 0, float(inner_rtol))
+    info = h2_solve_info()
+    rc = lib().h2_solve(h, b.data_ptr(), z.data_ptr(), C.byref(p), C.byref(info), _stream(stream))
+    if rc != H2_ENOTCONV or check:
+        _check(rc)
+    return dict(iterations=info.iterations, outer=info.outer, rel_residual=info.rel_residual,
+                seconds=info.seconds, converged=rc == H2_OK)
+
+
+def h2_info(h) -> dict:
+    s = h2_stats()
+    _check(lib().h2_info(h, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in h2_stats._fields_}
+
+
+def h2_free(h):
+    if h:
+        lib().h2_free(h)
+
+
+def h2_export(h, what, index=0, count=None, dtype=None):
+    """Host copy of structure or matrix data (see H2_X_* in include/h2.h)."""
+    info = h2_info(h)
+    nc, k = info["nclusters"], info["k"]
+    cplx = info["kernel"] == H2_HELMHOLTZ
+    sizes = {H2_X_PERM: (info["n"], np.int32), H2_X_CLUSTERS: (6 * nc, np.int32),
+             H2_X_BOXES: (6 * nc, np.float64), H2_X_ADM: (2 * info["n_adm"], np.int32),
+             H2_X_NEAR: (2 * info["n_near"], np.int32), H2_X_DFS: (nc, np.int32),
+             H2_X_E: (k * k, np.float64), H2_X_S: (k * k * (2 if cplx else 1), np.float64)}
+    if what in sizes:
+        cnt, dt = sizes[what]
+    else:
+        cnt, dt = count, np.float64
+    out = np.zeros(max(int(cnt), 1), dtype=dt)
+    _check(lib().h2_export(h, what, int(index), out.ctypes.data, int(cnt)))
+    return out[:cnt]
+
+
+def h2_profile(h, enable: bool):
+    _check(lib().h2_profile(h, 1 if enable else 0))
+
+
+def h2_profile_read(h):
+    ms = (C.c_double * H2_NPHASE)()
+    calls = (C.c_int64 * H2_NPHASE)()
+    _check(lib().h2_profile_read(h, ms, calls))
+    names = ["forward", "coupling", "down", "near", "total"]
+    return {nm: (ms[i], calls[i]) for i, nm in enumerate(names)}
+
+
+class H2Matrix:
+    """Owning wrapper: H2Matrix(vertices, triangles, ...) builds; .matvec / .solve apply."""
+
+    def __init__(self, vertices, triangles, **kw):
+        self.h = build_h2(vertices, triangles, **kw)
+        self.info = h2_info(self.h)
+        self.n = self.info["n"]
+
+    def matvec(self, x, y=None, alpha=1.0, acc64=False, stream=None):
+        import torch
+        if y is None:
+            y = torch.zeros_like(x)
+        return h2_matvec(self.h, x, y, alpha, acc64, stream)
+
+    def solve(self, b, z=None, **kw):
+        import torch
+        if z is None:
+            z = torch.zeros_like(b)
+        return z, h2_solve(self.h, b, z, **kw)
+
+    def export(self, what, index=0, count=None):
+        return h2_export(self.h, what, index, count)
+
+    def close(self):
+        h2_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.close()
+        except Exception:
+            pass

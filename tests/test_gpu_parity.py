@@ -1,0 +1,175 @@
+"""GPU parity: the HIP H^2 product against the FP64 oracle (through the C ABI).
+
+Tolerances (relative, 2-norm over the compared entries):
+  FP64 storage                 1e-12  (rounding only; the quadrature rules and
+                                       conventions are the same on both sides)
+  FP32 storage, FP32 accum.    1e-6   (unit roundoff 6e-8 of stored entries and
+                                       partial sums, far below the H^2 error)
+  FP32 storage, FP64 accum.    1e-6
+  BF16 coupling, FP32 else     2e-3   (unit roundoff 4e-3 of S entries, averaged
+                                       over the k = 27..64 terms of each product)
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import h2_inputs as I
+from oracle.h2 import H2Oracle
+from oracle.kernels import Kernel
+from tests.closed_forms import poly_kernel_product
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_05665_amd import h2  # noqa: E402
+
+TOL = {"f64": 1e-12, "f32": 1e-6, "f32_sbf16": 2e-3}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle(kind, level, m, leaf, eta=0.5, kernel=0, kappa=0.0):
+    V, T = I.mesh_for(kind, level)
+    return H2Oracle(V, T, Kernel(kernel, kappa), m=m, leaf=leaf, eta=eta)
+
+
+def gpu_matvec(A, x, y0=None, alpha=1.0, acc64=False, dtype=torch.float64):
+    xd = torch.tensor(x, dtype=dtype, device="cuda")
+    yd = torch.zeros_like(xd) if y0 is None else torch.tensor(y0, dtype=dtype, device="cuda")
+    A.matvec(xd, yd, alpha=alpha, acc64=acc64)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32_sbf16"])
+@pytest.mark.parametrize("case", [("sphere", 3, 3, 32), ("sphere", 3, 4, 16), ("cube", 16, 3, 32),
+                                  ("sphere", 2, 4, 24)])
+def test_matvec_matches_oracle(case, storage):
+    kind, level, m, leaf = case
+    H = oracle(kind, level, m, leaf)
+    V, T = H.mesh.V, H.mesh.T
+    print("case", case, storage, flush=True)
+    x = I.random_vector(H.mesh.n, 1, "uniform")
+    ref = H.matvec(x)
+    A = h2.H2Matrix(V, T, order=m, leaf=leaf, eta=0.5, storage=storage)
+    try:
+        y = gpu_matvec(A, x)
+        assert rel(y, ref) <= TOL[storage], rel(y, ref)
+        if storage != "f64":
+            y64 = gpu_matvec(A, x, acc64=True)
+            assert rel(y64, ref) <= TOL[storage]
+    finally:
+        A.close()
+
+
+def test_assembled_data_matches_oracle():
+    H = oracle("sphere", 3, 4, 16)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=4, leaf=16, eta=0.5, storage="f64")
+    try:
+        dfs = A.export(h2.H2_X_DFS)
+        cl = A.export(h2.H2_X_CLUSTERS).reshape(-1, 6)
+        adm = A.export(h2.H2_X_ADM).reshape(-1, 2)
+        near = A.export(h2.H2_X_NEAR).reshape(-1, 2)
+        for c in range(cl.shape[0]):
+            o = H.tree.clusters[dfs[c]]
+            if o.is_leaf:
+                Vl = A.export(h2.H2_X_V, c, count=o.idx.size * 64).reshape(-1, 64)
+                assert np.abs(Vl - H.V(o)).max() <= 1e-14 * np.abs(H.V(o)).max()
+            if c > 0:
+                E = A.export(h2.H2_X_E, c).reshape(64, 64)
+                assert np.abs(E - H.E(o)).max() <= 1e-13
+        for b in range(0, adm.shape[0], 97):
+            t, s = H.tree.clusters[dfs[adm[b, 0]]], H.tree.clusters[dfs[adm[b, 1]]]
+            S = A.export(h2.H2_X_S, b).reshape(64, 64)
+            assert np.abs(S - H.S(t, s)).max() <= 1e-14 * np.abs(S).max()
+        for b in range(0, near.shape[0], 13):
+            t, s = H.tree.clusters[dfs[near[b, 0]]], H.tree.clusters[dfs[near[b, 1]]]
+            N = A.export(h2.H2_X_N, b, count=t.idx.size * s.idx.size).reshape(t.idx.size, s.idx.size)
+            ref = H.N(t, s)
+            assert np.abs(N - ref).max() <= 1e-14 * np.abs(ref).max()
+    finally:
+        A.close()
+
+
+def test_accumulate_alpha_and_float32_vectors():
+    H = oracle("sphere", 3, 3, 32)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=3, leaf=32, eta=0.5, storage="f64")
+    try:
+        x = I.random_vector(H.mesh.n, 3, "normal")
+        y0 = I.random_vector(H.mesh.n, 4, "normal")
+        y = gpu_matvec(A, x, y0, alpha=-0.75)
+        ref = y0 - 0.75 * H.matvec(x)
+        assert rel(y, ref) <= 1e-12
+        y32 = gpu_matvec(A, x, dtype=torch.float32)
+        assert rel(y32, H.matvec(x)) <= 1e-6
+    finally:
+        A.close()
+
+
+def test_multiple_rhs_and_determinism():
+    H = oracle("sphere", 3, 3, 32)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=3, leaf=32, eta=0.5, storage="f32")
+    try:
+        X = I.random_vector(H.mesh.n, 9, "normal", nrhs=3)
+        xd = torch.tensor(X, dtype=torch.float64, device="cuda").t().contiguous().t()
+        yd = torch.zeros_like(xd)
+        A.matvec(xd, yd)
+        y1 = yd.cpu().numpy()
+        yd.zero_()
+        A.matvec(xd, yd)
+        y2 = yd.cpu().numpy()
+        assert np.array_equal(y1, y2)
+        for j in range(3):
+            single = gpu_matvec(A, X[:, j].copy())
+            assert np.array_equal(single, y1[:, j])
+    finally:
+        A.close()
+
+
+@pytest.mark.parametrize("case", [("sphere", 0, 2, 32), ("sphere", 1, 1, 8), ("sphere", 1, 2, 3),
+                                  ("cube", 2, 2, 4), ("sphere", 2, 5, 40)])
+def test_edge_cases(case):
+    """Single leaf (no admissible block), m = 1 (k = 1), tiny leaves, k = 125 > 64."""
+    kind, level, m, leaf = case
+    H = oracle(kind, level, m, leaf)
+    x = I.random_vector(H.mesh.n, 2, "uniform")
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage="f64")
+    try:
+        assert rel(gpu_matvec(A, x), H.matvec(x)) <= 1e-12
+    finally:
+        A.close()
+
+
+def test_empty_nrhs_and_bad_arguments():
+    V, T = I.icosphere(1)
+    A = h2.H2Matrix(V, T, order=2, leaf=8)
+    try:
+        x = torch.zeros(T.shape[0], 0, dtype=torch.float64, device="cuda")
+        assert h2.lib().h2_matvec(A.h, 0, 0, x.data_ptr(), T.shape[0], x.data_ptr(), T.shape[0], 1.0, 0,
+                                  None) == 0
+        with pytest.raises(h2.H2Error):
+            h2.h2_matvec(A.h, torch.zeros(5, dtype=torch.float64, device="cuda"),
+                         torch.zeros(5, dtype=torch.float64, device="cuda"))
+        assert h2.lib().h2_matvec(A.h, 1, 7, x.data_ptr(), T.shape[0], x.data_ptr(), T.shape[0], 1.0, 0,
+                                  None) == h2.H2_EINVAL
+    finally:
+        A.close()
+
+
+@pytest.mark.parametrize("kernel,m,name", [("one", 1, "one"), ("bilinear", 2, "bilinear"),
+                                           ("quadratic", 4, "quadratic")])
+@pytest.mark.parametrize("mesh", [("sphere", 6), ("cube", 64)])
+def test_closed_forms_medium(kernel, m, name, mesh):
+    V, T = I.mesh_for(*mesh)
+    x = I.random_vector(T.shape[0], 5, "normal")
+    ref = poly_kernel_product(V, T, name, x)
+    A = h2.H2Matrix(V, T, kernel=kernel, order=m, leaf=64, eta=0.5, storage="f64")
+    try:
+        assert A.info["n_adm"] > 0
+        assert rel(gpu_matvec(A, x), ref) <= 1e-12
+    finally:
+        A.close()

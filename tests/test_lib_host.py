@@ -1,0 +1,95 @@
+"""CPU tests of the HIP library: it loads, exports the declared ABI, and its
+host-side trees equal the oracle's exactly (no GPU needed: H2_HOST_ONLY)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import h2_inputs as I
+from paper_2203_05665_amd import h2
+from tests.oracle_cache import cube, sphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "h2.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert {"build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_free", "h2_last_error"} <= set(names)
+    L = ctypes.CDLL(h2.LIBPATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_errors_are_reported():
+    V, T = I.icosphere(1)
+    with pytest.raises(h2.H2Error) as e:
+        h2.build_h2(V, T, order=0, host_only=True)
+    assert e.value.code == h2.H2_EINVAL and "order" in h2.h2_last_error()
+    bad = T.copy()
+    bad[0, 0] = 10 ** 6
+    with pytest.raises(h2.H2Error):
+        h2.build_h2(V, bad, host_only=True)
+
+
+def _compare(H, lib_handle):
+    info = h2.h2_info(lib_handle)
+    tr = H.tree
+    assert info["nclusters"] == len(tr.clusters)
+    assert info["n_adm"] == len(H.adm) and info["n_near"] == len(H.inadm)
+    perm = h2.h2_export(lib_handle, h2.H2_X_PERM)
+    assert np.array_equal(perm, tr.perm)
+    cl = h2.h2_export(lib_handle, h2.H2_X_CLUSTERS).reshape(-1, 6)
+    bx = h2.h2_export(lib_handle, h2.H2_X_BOXES).reshape(-1, 6)
+    dfs = h2.h2_export(lib_handle, h2.H2_X_DFS)
+    key_lib = {}
+    for c in range(cl.shape[0]):
+        o = tr.clusters[dfs[c]]
+        assert (o.begin, o.end, o.level) == (cl[c, 0], cl[c, 1], cl[c, 5])
+        assert np.array_equal(bx[c, :3], o.lo) and np.array_equal(bx[c, 3:], o.hi)
+        assert o.is_leaf == (cl[c, 3] < 0)
+        key_lib[c] = (o.begin, o.end, o.level)
+    key_or = lambda c: (c.begin, c.end, c.level)
+    adm = h2.h2_export(lib_handle, h2.H2_X_ADM).reshape(-1, 2)
+    near = h2.h2_export(lib_handle, h2.H2_X_NEAR).reshape(-1, 2)
+    assert {(key_lib[a], key_lib[b]) for a, b in adm} == {(key_or(t), key_or(s)) for t, s in H.adm}
+    assert {(key_lib[a], key_lib[b]) for a, b in near} == {(key_or(t), key_or(s)) for t, s in H.inadm}
+    return info
+
+
+@pytest.mark.parametrize("which", ["sphere3_m3_l32", "sphere4_m4_l64", "cube16_m3_l32", "sphere3_eta1"])
+def test_structure_equals_oracle(which):
+    H = {"sphere3_m3_l32": lambda: sphere(3, 3, 32), "sphere4_m4_l64": lambda: sphere(4, 4, 64),
+         "cube16_m3_l32": lambda: cube(16, 3, 32), "sphere3_eta1": lambda: sphere(3, 3, 32, 1.0)}[which]()
+    V, T = H.mesh.V, H.mesh.T
+    hdl = h2.build_h2(V, T, order=H.m, leaf=H.tree.leaf, eta=H.eta, host_only=True)
+    try:
+        info = _compare(H, hdl)
+        assert info["near_entries"] == sum(t.idx.size * s.idx.size for t, s in H.inadm)
+    finally:
+        h2.h2_free(hdl)
+
+
+def test_structure_counts_at_full_size():
+    """1,310,720-triangle sphere, m = 4, leaf 64: the trees build on the host and
+    every index lands in exactly one leaf."""
+    V, T = I.icosphere(8)
+    hdl = h2.build_h2(V, T, order=4, leaf=64, eta=0.5, host_only=True)
+    try:
+        info = h2.h2_info(hdl)
+        perm = h2.h2_export(hdl, h2.H2_X_PERM)
+        assert np.array_equal(np.sort(perm), np.arange(T.shape[0]))
+        cl = h2.h2_export(hdl, h2.H2_X_CLUSTERS).reshape(-1, 6)
+        leaves = cl[cl[:, 3] < 0]
+        assert (leaves[:, 1] - leaves[:, 0]).sum() == T.shape[0]
+        assert (leaves[:, 1] - leaves[:, 0]).max() <= 64
+        assert info["n_adm"] > 0 and info["near_entries"] > 0
+    finally:
+        h2.h2_free(hdl)
