@@ -99,8 +99,36 @@ __global__ void permute_out(int64_t n, const int32_t* __restrict__ perm, const A
   }
 }
 
+// ---------------------------------------------------------------- wave broadcast
+// value of lane `j` (wave-uniform) to every lane
+__device__ inline float bcast(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ inline double bcast(double v, int j) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffff), j);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), j);
+  return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+
+// acc += sum_{j < cnt} A[j * stride] * (value of xv in lane j), 8 loads in flight
+template <typename ST, typename AT>
+__device__ inline AT stream_dot(const ST* __restrict__ A, int64_t stride, int cnt, AT xv, AT acc) {
+  int j = 0;
+  for (; j + 8 <= cnt; j += 8) {
+    AT a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = ld<ST, AT>(A + (j + u) * stride);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += a[u] * bcast(xv, j + u);
+  }
+  for (; j < cnt; ++j) acc += ld<ST, AT>(A + j * stride) * bcast(xv, j);
+  return acc;
+}
+
 // ---------------------------------------------------------------- leaf forward
-// one wave per leaf, lane = nu (loops for k > 64)
+// one wave per leaf, lane = nu (chunks of 64 for k > 64); x|sigma staged one
+// value per lane and broadcast
 template <typename ST, typename AT>
 __global__ __launch_bounds__(256) void leaf_forward(int nleaves, int k, const int32_t* __restrict__ leaves,
                                                     const int32_t* __restrict__ cbegin,
@@ -110,11 +138,17 @@ __global__ __launch_bounds__(256) void leaf_forward(int nleaves, int k, const in
   const int lane = threadIdx.x % 64;
   if (l >= nleaves) return;
   const int32_t c = leaves[l];
-  const int64_t b0 = cbegin[c], e0 = cend[c];
-  for (int nu = lane; nu < k; nu += 64) {
+  const int64_t b0 = cbegin[c];
+  const int r = cend[c] - cbegin[c];
+  for (int nu0 = 0; nu0 < k; nu0 += 64) {
+    const int nu = nu0 + lane;
+    const int nus = nu < k ? nu : 0;
     AT acc = 0;
-    for (int64_t p = b0; p < e0; ++p) acc += ld<ST, AT>(Vf + p * k + nu) * xc[p];
-    xhat[static_cast<int64_t>(c) * k + nu] = acc;
+    for (int p0 = 0; p0 < r; p0 += 64) {
+      const AT xv = p0 + lane < r ? xc[b0 + p0 + lane] : AT(0);
+      acc = stream_dot<ST, AT>(Vf + (b0 + p0) * k + nus, k, min(64, r - p0), xv, acc);
+    }
+    if (nu < k) xhat[static_cast<int64_t>(c) * k + nu] = acc;
   }
 }
 
@@ -131,14 +165,18 @@ __global__ __launch_bounds__(256) void transfer_up(int count, int k, const int32
   const int32_t c = list[w];
   const int32_t ch[2] = {child0[c], child1[c]};
   const int64_t kk = static_cast<int64_t>(k) * k;
-  for (int nu = lane; nu < k; nu += 64) {
+  for (int nu0 = 0; nu0 < k; nu0 += 64) {
+    const int nu = nu0 + lane;
+    const int nus = nu < k ? nu : 0;
     AT acc = 0;
     for (int a = 0; a < 2; ++a) {
-      const ST* Fc = F + ch[a] * kk;
       const AT* xs = xhat + static_cast<int64_t>(ch[a]) * k;
-      for (int nup = 0; nup < k; ++nup) acc += ld<ST, AT>(Fc + static_cast<int64_t>(nup) * k + nu) * xs[nup];
+      for (int q0 = 0; q0 < k; q0 += 64) {
+        const AT xv = q0 + lane < k ? xs[q0 + lane] : AT(0);
+        acc = stream_dot<ST, AT>(F + ch[a] * kk + static_cast<int64_t>(q0) * k + nus, k, min(64, k - q0), xv, acc);
+      }
     }
-    xhat[static_cast<int64_t>(c) * k + nu] = acc;
+    if (nu < k) xhat[static_cast<int64_t>(c) * k + nu] = acc;
   }
 }
 
@@ -151,12 +189,16 @@ __global__ __launch_bounds__(256) void transfer_down(int first, int count, int k
   if (w >= count) return;
   const int32_t c = first + w;
   const int64_t kk = static_cast<int64_t>(k) * k;
-  const ST* Ec = ET + c * kk;
   const AT* yp = yhat + static_cast<int64_t>(parent[c]) * k;
-  for (int nup = lane; nup < k; nup += 64) {
+  for (int n0 = 0; n0 < k; n0 += 64) {
+    const int nup = n0 + lane;
+    const int nus = nup < k ? nup : 0;
     AT acc = 0;
-    for (int nu = 0; nu < k; ++nu) acc += ld<ST, AT>(Ec + static_cast<int64_t>(nu) * k + nup) * yp[nu];
-    yhat[static_cast<int64_t>(c) * k + nup] += acc;
+    for (int q0 = 0; q0 < k; q0 += 64) {
+      const AT yv = q0 + lane < k ? yp[q0 + lane] : AT(0);
+      acc = stream_dot<ST, AT>(ET + c * kk + static_cast<int64_t>(q0) * k + nus, k, min(64, k - q0), yv, acc);
+    }
+    if (nup < k) yhat[static_cast<int64_t>(c) * k + nup] += acc;
   }
 }
 
@@ -238,8 +280,12 @@ __global__ __launch_bounds__(256) void coupling_any(int nc, int k, const int64_t
 }
 
 // ---------------------------------------------------------------- near field + leaf backward
-// one 256-thread workgroup per row leaf; lane = row of the leaf, the four waves
-// take every fourth column of the panel; LDS sums the four partial results.
+// one 256-thread workgroup per row leaf tau; lane = row of tau.  The near blocks
+// of the row are dealt round-robin to the four waves; a wave stages x|sigma one
+// value per lane and streams the block's columns (each column is |tau|
+// contiguous entries of the column-major panel) with 8 loads in flight.  The
+// columns of V_tau (multiplied by y^_tau) are split between the waves the same
+// way.  LDS sums the four partial results in a fixed order.
 template <typename ST, typename AT>
 __global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const int32_t* __restrict__ leaves,
                                                      const int32_t* __restrict__ cbegin,
@@ -255,29 +301,39 @@ __global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const i
   if (l >= nleaves) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int32_t tau = leaves[l];
-  const int64_t b0 = cbegin[tau], r = cend[tau] - b0;
+  const int64_t b0 = cbegin[tau];
+  const int r = cend[tau] - cbegin[tau];
   const ST* P = N + panel_off[l];
   const ST* Vl = Vb + b0 * k;
   const AT* yh = yhat + static_cast<int64_t>(tau) * k;
-  for (int64_t i0 = 0; i0 < r; i0 += 64) {
-    const int64_t i = i0 + lane;
-    const bool on = i < r;
+  const int64_t bfirst = near_ptr[l], blast = near_ptr[l + 1];
+  for (int i0 = 0; i0 < r; i0 += 64) {
+    const int i = i0 + lane;
+    const int is = i < r ? i : r - 1;  // idle lanes re-read the last row
     AT acc = 0;
     int64_t colbase = 0;
-    for (int64_t bb = near_ptr[l]; bb < near_ptr[l + 1]; ++bb) {
+    for (int64_t bb = bfirst; bb < blast; ++bb) {
       const int32_t s = near_col[bb];
-      const int64_t s0 = cbegin[s], w = cend[s] - s0;
-      if (on) {
-        const ST* Pc = P + colbase * r + i;
-        for (int64_t j = wave; j < w; j += 4) acc += ld<ST, AT>(Pc + j * r) * xc[s0 + j];
+      const int64_t s0 = cbegin[s];
+      const int w = cend[s] - cbegin[s];
+      if (((bb - bfirst) & 3) == wave) {
+        for (int j0 = 0; j0 < w; j0 += 64) {
+          const AT xv = j0 + lane < w ? xc[s0 + j0 + lane] : AT(0);
+          acc = stream_dot<ST, AT>(P + (colbase + j0) * r + is, r, min(64, w - j0), xv, acc);
+        }
       }
       colbase += w;
     }
-    if (on)
-      for (int nu = wave; nu < k; nu += 4) acc += ld<ST, AT>(Vl + static_cast<int64_t>(nu) * r + i) * yh[nu];
+    // leaf backward: columns nu of V_tau, a quarter per wave
+    const int kq = (k + 3) / 4;
+    const int n0 = wave * kq, n1 = min(k, n0 + kq);
+    for (int q0 = n0; q0 < n1; q0 += 64) {
+      const AT yv = q0 + lane < n1 ? yh[q0 + lane] : AT(0);
+      acc = stream_dot<ST, AT>(Vl + static_cast<int64_t>(q0) * r + is, r, min(64, n1 - q0), yv, acc);
+    }
     part[wave][lane] = acc;
     __syncthreads();
-    if (wave == 0 && on) yc[b0 + i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (wave == 0 && i < r) yc[b0 + i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     __syncthreads();
   }
 }
