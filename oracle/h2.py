@@ -186,11 +186,47 @@ class H2Oracle:
             stack.extend((a, b) for a, b in ch if a.id in path)
         return adm, inadm
 
-    def sampled_rows(self, x, leaf_ids, xhat=None):
+    def forward_sparse(self, x, support):
+        """Algorithm 1 for an x that vanishes outside the given leaf clusters.
+
+        A cluster containing none of the support leaves has x|sigma = 0 and hence
+        x-hat_sigma = 0, so the recursion only descends into clusters that contain
+        support; all other entries of the returned list are exact zeros.
+        """
+        x = np.asarray(x)
+        dt = np.result_type(x, self.g.dtype)
+        keep = set()
+        for lid in support:
+            c = self.tree.clusters[lid]
+            while c is not None:
+                keep.add(c.id)
+                c = c.parent
+        xhat = [None] * len(self.tree.clusters)
+
+        def fwd(sig):
+            if sig.is_leaf:
+                xhat[sig.id] = self.V(sig).T @ x[sig.idx]
+                return
+            acc = np.zeros(self.k, dtype=dt)
+            for ch in sig.children:
+                if ch.id in keep:
+                    fwd(ch)
+                    acc = acc + self.E(ch).T @ xhat[ch.id]
+            xhat[sig.id] = acc
+
+        fwd(self.tree.root)
+        zero = np.zeros(self.k, dtype=dt)
+        return [zero if v is None else v for v in xhat], keep
+
+    def sampled_rows(self, x, leaf_ids, xhat=None, support=None):
         """(G-tilde x)|leaf for each requested leaf cluster id -> dict id -> (rows idx, values)."""
         x = np.asarray(x)
+        keep = None
         if xhat is None:
-            xhat = self.all_xhat(x)
+            if support is None:
+                xhat = self.all_xhat(x)
+            else:
+                xhat, keep = self.forward_sparse(x, support)
         out = {}
         for lid in leaf_ids:
             leaf = self.tree.clusters[lid]
@@ -199,11 +235,15 @@ class H2Oracle:
             y = np.zeros(leaf.idx.size, dtype=np.result_type(x, self.g.dtype))
             pos = {int(i): r for r, i in enumerate(leaf.idx)}
             for t, s in adm:
+                if keep is not None and s.id not in keep:
+                    continue                        # x-hat_sigma = 0
                 rows = np.array([pos[int(i)] for i in leaf.idx])
                 # rows of V_t that belong to the leaf, evaluated from eq. (leafV) on t's box
                 Vt = IP.basis_matrix(t, self.m, self.mesh, leaf.idx)
                 y[rows] += Vt @ (self.S(t, s, store=False) @ xhat[s.id])
             for t, s in inadm:
+                if keep is not None and s.id not in keep:
+                    continue                        # x|sigma = 0
                 y += self.nf.block(leaf.idx, s.idx) @ x[s.idx]
             out[lid] = (leaf.idx.copy(), y)
         return out

@@ -1,0 +1,106 @@
+"""GPU parity at the measured sizes, in the configuration bench.py times
+(m = 4, k = 64, leaf 64, eta = 1/2, the coupling64 / near_backward kernels).
+
+* Closed forms hold at any size: with the polynomial kernels g = (x.y)^2
+  (interpolated exactly at m = 4) the product has a closed form through the
+  triangles' second moments, so every block of the 1,310,720-triangle sphere
+  and of the 786,432-triangle cube surface is checked with a dense x.
+* Laplace at 1,310,720 triangles: x supported on a few leaf clusters, rows of
+  sampled leaves computed one by one by the oracle (sparse forward transform).
+* Laplace at 327,680 triangles: dense x, rows of sampled leaves by the oracle.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import h2_inputs as I
+from oracle.h2 import H2Oracle
+from oracle.kernels import Kernel
+from tests.closed_forms import poly_kernel_product
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_05665_amd import h2  # noqa: E402
+
+# FP64: relative to ||G~ x||; FP32: relative to ||G~ |x| || (the scale of a
+# floating-point sum; see test_gpu_parity.py)
+TOL = {"f64": 1e-12, "f32": 1e-6, "f32_sbf16": 2e-3}
+
+
+def err(storage, y, ref, ref_abs):
+    scale = ref if storage == "f64" else ref_abs
+    return float(np.linalg.norm(y - ref) / np.linalg.norm(scale))
+
+
+def run(A, x):
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+    yd = torch.zeros_like(xd)
+    A.matvec(xd, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+@pytest.mark.parametrize("mesh", [("sphere", 8), ("cube", 256)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_closed_form_full_size(mesh, storage):
+    print("closed form", mesh, storage, flush=True)
+    V, T = I.mesh_for(*mesh)
+    x = I.random_vector(T.shape[0], 3, "normal")
+    ref = poly_kernel_product(V, T, "quadratic", x)
+    ref_abs = poly_kernel_product(V, T, "quadratic", np.abs(x))   # g >= 0: |G| |x| = G |x|
+    A = h2.H2Matrix(V, T, kernel="quadratic", order=4, leaf=64, eta=0.5, storage=storage)
+    try:
+        assert A.info["n_adm"] > 10 ** 5
+        assert err(storage, run(A, x), ref, ref_abs) <= TOL[storage]
+    finally:
+        A.close()
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_tree(kind, level):
+    V, T = I.mesh_for(kind, level)
+    return H2Oracle(V, T, Kernel(), m=4, leaf=64, eta=0.5, build_blocks=False)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_laplace_sampled_rows_1310k(storage):
+    print("laplace sampled rows 1310k", storage, flush=True)
+    H = oracle_tree("sphere", 8)
+    rng = np.random.default_rng(17)
+    leaves = H.tree.leaves
+    support = [leaves[i].id for i in rng.choice(len(leaves), 12, replace=False)]
+    x = np.zeros(H.mesh.n)
+    for lid in support:
+        c = H.tree.clusters[lid]
+        x[c.idx] = rng.standard_normal(c.idx.size)
+    sample = [leaves[i].id for i in rng.choice(len(leaves), 10, replace=False)] + support[:4]
+    ref = H.sampled_rows(x, sample, support=support)
+    ref_abs = H.sampled_rows(np.abs(x), sample, support=support)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=4, leaf=64, eta=0.5, storage=storage)
+    try:
+        y = run(A, x)
+    finally:
+        A.close()
+    rows = np.concatenate([v[0] for v in ref.values()])
+    val = np.concatenate([v[1] for v in ref.values()])
+    val_abs = np.concatenate([v[1] for v in ref_abs.values()])
+    assert err(storage, y[rows], val, val_abs) <= TOL[storage]
+
+
+def test_laplace_sampled_rows_327k_dense_x():
+    print("laplace sampled rows 327k", flush=True)
+    H = oracle_tree("sphere", 7)
+    x = I.random_vector(H.mesh.n, 2, "normal")
+    rng = np.random.default_rng(2)
+    sample = [H.tree.leaves[i].id for i in rng.choice(len(H.tree.leaves), 4, replace=False)]
+    ref = H.sampled_rows(x, sample)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=4, leaf=64, eta=0.5, storage="f64")
+    try:
+        y = run(A, x)
+    finally:
+        A.close()
+    rows = np.concatenate([v[0] for v in ref.values()])
+    val = np.concatenate([v[1] for v in ref.values()])
+    assert err("f64", y[rows], val, None) <= 1e-12

@@ -1,13 +1,15 @@
 """GPU parity: the HIP H^2 product against the FP64 oracle (through the C ABI).
 
-Tolerances (relative, 2-norm over the compared entries):
-  FP64 storage                 1e-12  (rounding only; the quadrature rules and
-                                       conventions are the same on both sides)
-  FP32 storage, FP32 accum.    1e-6   (unit roundoff 6e-8 of stored entries and
-                                       partial sums, far below the H^2 error)
-  FP32 storage, FP64 accum.    1e-6
-  BF16 coupling, FP32 else     2e-3   (unit roundoff 4e-3 of S entries, averaged
-                                       over the k = 27..64 terms of each product)
+Tolerances (2-norm over the compared entries):
+  FP64 storage    ||y - y_ref|| <= 1e-12 ||G~ x||      (rounding only: quadrature
+                  rules and conventions are the same on both sides)
+  FP32 storage    ||y - y_ref|| <= 1e-6  ||G~ |x| ||   (FP32 unit roundoff 6e-8 of
+                  stored entries and partial sums; a floating-point sum is accurate
+                  relative to the sum of the absolute terms, and with x ~ N(0,1)
+                  the sums over all n columns cancel by a factor of order sqrt(n),
+                  so the scale is G~ applied to |x|, not G~ x)
+  BF16 coupling   ||y - y_ref|| <= 2e-3  ||G~ |x| ||   (BF16 unit roundoff 2e-3)
+The same bounds hold with FP64 accumulation over FP32/BF16 storage.
 """
 import functools
 
@@ -27,8 +29,13 @@ from paper_2203_05665_amd import h2  # noqa: E402
 TOL = {"f64": 1e-12, "f32": 1e-6, "f32_sbf16": 2e-3}
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+def rel(a, b, scale=None):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b if scale is None else scale))
+
+
+def err(storage, y, ref, ref_abs):
+    """Error in the norm the tolerance of `storage` is stated in."""
+    return rel(y, ref) if storage == "f64" else rel(y, ref, ref_abs)
 
 
 @functools.lru_cache(maxsize=None)
@@ -55,13 +62,14 @@ def test_matvec_matches_oracle(case, storage):
     print("case", case, storage, flush=True)
     x = I.random_vector(H.mesh.n, 1, "uniform")
     ref = H.matvec(x)
+    ref_abs = H.matvec(np.abs(x))
     A = h2.H2Matrix(V, T, order=m, leaf=leaf, eta=0.5, storage=storage)
     try:
         y = gpu_matvec(A, x)
-        assert rel(y, ref) <= TOL[storage], rel(y, ref)
+        assert err(storage, y, ref, ref_abs) <= TOL[storage]
         if storage != "f64":
             y64 = gpu_matvec(A, x, acc64=True)
-            assert rel(y64, ref) <= TOL[storage]
+            assert err(storage, y64, ref, ref_abs) <= TOL[storage]
     finally:
         A.close()
 
@@ -105,7 +113,7 @@ def test_accumulate_alpha_and_float32_vectors():
         ref = y0 - 0.75 * H.matvec(x)
         assert rel(y, ref) <= 1e-12
         y32 = gpu_matvec(A, x, dtype=torch.float32)
-        assert rel(y32, H.matvec(x)) <= 1e-6
+        assert rel(y32, H.matvec(x), H.matvec(np.abs(x))) <= 1e-6
     finally:
         A.close()
 

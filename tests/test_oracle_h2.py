@@ -120,3 +120,18 @@ def test_sampled_rows_match_full_product():
     ids = [c.id for c in H.tree.leaves[::7]]
     for lid, (rows, val) in H.sampled_rows(x, ids).items():
         assert np.abs(val - y[rows]).max() <= 1e-14 * np.abs(y).max()
+
+
+def test_sparse_support_rows_match_full_product():
+    """Rows computed with the sparse-support forward transformation equal the
+    rows of the full product for an x supported on a few leaves."""
+    H = sphere(3, 3, 32)
+    sup = [c.id for c in H.tree.leaves[3::11]]
+    x = np.zeros(H.mesh.n)
+    rng = np.random.default_rng(5)
+    for lid in sup:
+        x[H.tree.clusters[lid].idx] = rng.standard_normal(H.tree.clusters[lid].idx.size)
+    y = H.matvec(x)
+    ids = [c.id for c in H.tree.leaves[::5]] + sup[:2]
+    for lid, (rows, val) in H.sampled_rows(x, ids, support=sup).items():
+        assert np.abs(val - y[rows]).max() <= 1e-14 * np.abs(y).max()
