@@ -117,18 +117,48 @@ def cpu_baseline_sample(kind, level, order, leaf, seed, budget_s=25.0):
     _h2.h2_free(hh)
     est = (t_fwd + t_bwd) * ncl / nsub + t_adm * info["n_adm"] / max(1, len(adm)) + \
         t_near * info["n_near"] / max(1, len(near))
-    cores = 1
-    try:
-        import threadpoolctl
-        for p in threadpoolctl.threadpool_info():
-            cores = max(cores, int(p.get("num_threads", 1)))
-    except Exception:
-        pass
+    cores = 1  # the oracle is sequential Python/NumPy; BLAS is pinned to one thread below
     sample = ("oracle Algorithms 1-2 on a depth-5 subtree (%d of %d clusters) and Algorithm 3 on %d "
               "admissible + %d inadmissible blocks (block rows of random leaves), FP64, matrices pre-assembled; "
               "scaled to the whole product" % (nsub, ncl, len(adm), len(near)))
     return {"value": 1.0 / est, "unit": "H2 matvecs/s", "cores": cores, "kind": "oracle",
             "sample": sample, "est_seconds_per_matvec": est}
+
+
+def copy_probe(torch, gib=2.0, reps=5):
+    """Device-to-device copy of a known size: measured HBM rate (read + write bytes)."""
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * 4 * n, "GBs": 2 * 4 * n * reps / el / 1e9}
+
+
+def recorded_traffic(workload):
+    """HBM bytes per coupling launch from the committed PMC summary, or None if the
+    kernel source changed since the counters were taken (or none were taken)."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "coupling64_%s_pmc.md" % workload)
+    src = os.path.join(ROOT, "paper_2203_05665_amd", "csrc", "matvec.hip")
+    if not os.path.exists(prof):
+        return None
+    text = open(prof).read()
+    mt = re.search(r"traffic_bytes_per_launch coupling64: (\d+)", text)
+    mh = re.search(r"matvec.hip sha256 prefix: ([0-9a-f]+)", text)
+    if not (mt and mh):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != mh.group(1):
+        return None
+    return float(mt.group(1))
 
 
 def _walk(c):
@@ -145,6 +175,7 @@ def main():
     ap.add_argument("--workload", default="sphere1310k_m4_f32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison run")
+    ap.add_argument("--copy-probe", action="store_true", help="also time a device copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the H^2 product here runs on a single MI355X "
@@ -187,7 +218,8 @@ def main():
                    "order_m": order, "k": order ** 3, "leaf": leaf, "eta": 0.5, "storage": storage,
                    "accumulate": "f64" if storage == "f64" else "f32", "rhs": 1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "coupling64",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.workload),
+                     "kernel": "coupling64",
                      "algorithmic_bytes_per_launch": coup_bytes, "avg_launch_ms": coup_avg_ms},
         "path": {"algorithmic_bytes": info["matvec_bytes"],
                  "achieved_GBs": info["matvec_bytes"] / (el / args.steps) / 1e9,
@@ -211,10 +243,14 @@ def main():
                                "frac_hbm_peak": B.info["matvec_bytes"] / (el64 / st64) / 1e9 / HBM_PEAK_GBS,
                                "speedup_f32_over_f64": (args.steps / el) / (st64 / el64)}
         B.close()
+    if args.copy_probe:
+        out["copy_probe"] = copy_probe(torch)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle sample")
         try:
-            out["cpu_baseline"] = cpu_baseline_sample(kind, level, order, leaf, seed)
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                out["cpu_baseline"] = cpu_baseline_sample(kind, level, order, leaf, seed)
         except Exception as e:  # the baseline is a report, never a reason to lose the line
             out["cpu_baseline"] = {"value": None, "error": repr(e)}
     print(json.dumps(out), flush=True)
