@@ -32,6 +32,9 @@ WORKLOADS = {
     "sphere327k_m4_f64": ("sphere", 7, 4, 64, "f64", 2),
     "cube786k_m4_f32": ("cube", 256, 4, 64, "f32", 4),
 }
+# many right-hand sides: (mesh kind, level, order, leaf, storage, seed, nrhs)
+MULTI = {"cube786k_m4_r64": ("cube", 256, 4, 64, "f32", 4, 64)}
+MFMA_F32_PEAK_TFS = 157.3
 
 
 def log(*a):
@@ -167,12 +170,62 @@ def _walk(c):
         yield from _walk(ch)
 
 
+def bench_multi(args):
+    """Many right-hand sides in one call (matrix-core path)."""
+    import torch
+
+    import h2_inputs as I
+    from paper_2203_05665_amd import h2
+
+    kind, level, order, leaf, storage, seed, R = MULTI[args.workload]
+    V, T = I.mesh_for(kind, level)
+    n = T.shape[0]
+    log("bench: %s n=%d m=%d leaf=%d storage=%s nrhs=%d" % (args.workload, n, order, leaf, storage, R))
+    t0 = time.perf_counter()
+    A = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = A.info
+    X = torch.tensor(I.random_vector(n, seed, "normal", nrhs=R), dtype=torch.float64, device="cuda")
+    X = X.t().contiguous().t()
+    Y = torch.zeros_like(X)
+    el, prof = measure(A, X, Y, args.steps, args.warmup, torch, h2)
+    k = info["k"]
+    flops_total = info["matvec_flops"] * R
+    coup_flops = 2.0 * k * k * info["n_adm"] * R
+    coup_ms = prof["coupling"][0] / max(1, prof["coupling"][1])
+    achieved = coup_flops / (coup_ms * 1e-3) / 1e12
+    out = {
+        "metric": "RHS x H2 matvecs/s", "value": R * args.steps / el, "unit": "rhs-matvec/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "mesh": "%s level %d" % (kind, level), "triangles": n,
+                   "order_m": order, "k": k, "leaf": leaf, "eta": 0.5, "storage": storage, "rhs": R},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_F32_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_F32_PEAK_TFS, "traffic": None, "kernel": "mcoupling",
+                     "algorithmic_flops_per_launch": coup_flops, "avg_launch_ms": coup_ms},
+        "path": {"flops": flops_total, "TFLOPs": flops_total / (el / args.steps) / 1e12,
+                 "phase_ms": {kk: v[0] / max(1, v[1]) for kk, v in prof.items()}, "build_s": build_s,
+                 "device_bytes": info["bytes_total"]},
+    }
+    A.close()
+    # the same columns one at a time, for comparison
+    B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
+    x1 = X[:, 0].contiguous()
+    y1 = torch.zeros_like(x1)
+    el1, _ = measure(B, x1, y1, max(3, args.steps), 1, torch, h2)
+    out["single_rhs_compare"] = {"value": max(3, args.steps) / el1, "unit": "matvec/s",
+                                 "speedup_per_rhs": (R * args.steps / el) / (max(3, args.steps) / el1)}
+    B.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sphere1310k_m4_f32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="sphere1310k_m4_f32", choices=sorted(WORKLOADS) + sorted(MULTI))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison run")
     ap.add_argument("--copy-probe", action="store_true", help="also time a device copy of known size")
@@ -188,6 +241,8 @@ def main():
     import h2_inputs as I
     from paper_2203_05665_amd import h2
 
+    if args.workload in MULTI:
+        return bench_multi(args)
     kind, level, order, leaf, storage, seed = WORKLOADS[args.workload]
     V, T = I.mesh_for(kind, level)
     n = T.shape[0]

@@ -76,6 +76,8 @@ struct h2_handle_s {
   h2::DBuf Vf, Vb, F, ET, Smat, Nmat;
   // workspaces (sized for FP64 vectors, one right-hand side)
   h2::DBuf xc, yc, xhat, yhat;
+  // many-right-hand-side workspaces (FP32, grown on first use)
+  h2::DBuf mxc, myc, mxhat, myhat;
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> events;     // pool
@@ -89,6 +91,9 @@ namespace h2 {
 void assemble(h2_handle_s& H);  // fills Vf, Vb, F, ET, Smat, Nmat on the device
 void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
             double alpha, int flags, hipStream_t s);
+bool matvec_multi_supported(const h2_handle_s& H);
+void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
+                  double alpha, hipStream_t s);
 int solve(h2_handle_s& H, const double* b, double* z, const h2_solve_params& p, h2_solve_info& info,
           hipStream_t s);
 hipEvent_t prof_event(h2_handle_s& H);

@@ -431,6 +431,10 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
   if (ldx < H.S.n || ldy < H.S.n) throw Error(H2_EINVAL, "leading dimension smaller than n");
   const size_t es = dtype == H2_R64 ? 8 : 4;
   const bool acc64 = (flags & H2_ACC_F64) != 0;
+  if (nrhs >= 2 && !acc64 && matvec_multi_supported(H)) {
+    matvec_multi(H, nrhs, dtype, x, ldx, y, ldy, alpha, st);
+    return;
+  }
   for (int j = 0; j < nrhs; ++j) {
     const void* xj = static_cast<const char*>(x) + static_cast<size_t>(j) * ldx * es;
     void* yj = static_cast<char*>(y) + static_cast<size_t>(j) * ldy * es;

@@ -1,0 +1,424 @@
+// Many right-hand sides: y <- y + alpha G~ X for an n x R block X (FP32 storage,
+// k = 64).  The phases are those of the single-vector product (Algorithms 1-3);
+// with R columns each step becomes a small dense contraction, evaluated on the
+// matrix cores with v_mfma_f32_32x32x2f32.
+//
+// Internal layouts (RP = 32 or 64 right-hand sides per pass, zero-padded):
+//   x_c, y_c   [n][RP]        position-major, right-hand sides contiguous
+//   x^, y^     [N_c][RP][k]   per cluster, the k coefficients of one right-hand
+//                             side contiguous
+// One wave owns one output block (a row cluster, a leaf or a transfer target)
+// and computes all of it: 2 x (RP/32) tiles of 32 x 32 (rows of k or of the leaf
+// x right-hand sides), so every input element is loaded once per block.  Row
+// clusters are dealt to the eight XCDs in contiguous chunks, so neighbouring
+// rows, which share most of their column clusters, share an L2.  Every output
+// element has one owner: no atomics.
+//
+// MFMA operand convention (K = 64 per call, split across lane halves): in each
+// step lanes 0-31 supply A[i][kk] and B[kk][j] for one kk of the first half of K
+// and lanes 32-63 those for one kk of the second half, i = j = lane % 32.
+// The 32 x 32 accumulator holds D[i][j] in register v of lane l with
+// j = l % 32, i = (v % 4) + 4 (l / 32) + 8 (v / 4).
+#include <hip/hip_runtime.h>
+
+#include "handle.h"
+
+namespace h2 {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ inline f32x16 mfma(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__device__ inline int acc_row(int v, int l) { return (v % 4) + 4 * (l / 32) + 8 * (v / 4); }
+
+__device__ inline f4v ld4c(const float* p) { return *reinterpret_cast<const f4v*>(p); }
+
+// acc[ti][tj] += A(rows 32ti.., 64) * B(64, cols 32tj..) for ti < 2, tj < NT.
+// A row-major 64 x 64 (row stride 64); Bt right-hand-side-major (element (kk, j)
+// at Bt[j * 64 + kk]).  In step (p, e) lane half h covers kk = 8 p + 4 h + e, so
+// the two lanes of a row read 32 contiguous bytes and the four steps p of one
+// half-block consume whole 128-byte lines back to back (cached loads: the lines
+// are reused by the next instructions, not streamed past).
+template <int NT>
+__device__ inline void mma64_rowA(const float* __restrict__ A, const float* __restrict__ Bt, f32x16 (&acc)[2][NT]) {
+  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    f4v a[2][4], b[NT][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 8 * (4 * half + q) + 4 * h;
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) a[ti][q] = ld4c(A + (32 * ti + r) * 64 + kk);
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) b[tj][q] = ld4c(Bt + (32 * tj + r) * 64 + kk);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma(a[ti][q][e], b[tj][q][e], acc[ti][tj]);
+  }
+}
+
+// acc[ti][tj] += A(rows < mrows, kcount) * B(kcount, cols) with A column-major
+// (element (i, kk) at A[kk * lda + i]) and B position-major (element (kk, j) at
+// B[kk * ldb + j]); 1 <= kcount <= 64, mrows >= 1, lda * 64 and ldb * 64 fit in
+// int; rows >= mrows and kk >= kcount count as zero.  Lane half h covers
+// kk = step + 32 h; one load instruction reads one column (or row) of 32
+// consecutive elements per lane half.  Every load reads a clamped in-range
+// address and the mask is applied by a select, so the loop has no divergent
+// control flow.
+template <int NT>
+__device__ inline void mma_colA(const float* __restrict__ A, int lda, int mrows, const float* __restrict__ B,
+                                int ldb, int kcount, f32x16 (&acc)[2][NT]) {
+  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+  const bool row0 = r < mrows, row1 = r + 32 < mrows;
+  const float* a0 = A + min(r, mrows - 1);
+  const float* a1 = A + min(r + 32, mrows - 1);
+  const float* b = B + r;
+  const int steps = min(32, kcount);
+#pragma unroll 2
+  for (int k0 = 0; k0 < steps; k0 += 4) {
+    float av[2][4], bv[NT][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + u + 32 * h;
+      const bool ok = kk < kcount;
+      const int kc = min(kk, kcount - 1);
+      const float x0 = a0[kc * lda], x1 = a1[kc * lda];
+      av[0][u] = (ok && row0) ? x0 : 0.f;
+      av[1][u] = (ok && row1) ? x1 : 0.f;
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const float y = b[kc * ldb + 32 * tj];
+        bv[tj][u] = ok ? y : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma(av[ti][u], bv[tj][u], acc[ti][tj]);
+  }
+}
+
+// acc[ti][tj] += A(rows < mrows, 64) * B(64, cols), A column-major (lda), Bt
+// right-hand-side-major (element (kk, j) at Bt[j * 64 + kk]); in step (p, e)
+// lane half h covers kk = 8 p + 4 h + e.  Clamped loads and selects as above.
+template <int NT>
+__device__ inline void mma_colA_Bt(const float* __restrict__ A, int lda, int mrows, const float* __restrict__ Bt,
+                                   f32x16 (&acc)[2][NT]) {
+  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+  const bool row0 = r < mrows, row1 = r + 32 < mrows;
+  const float* a0 = A + min(r, mrows - 1);
+  const float* a1 = A + min(r + 32, mrows - 1);
+#pragma unroll 2
+  for (int p = 0; p < 8; ++p) {
+    const int kk = 8 * p + 4 * h;
+    float av[2][4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float x0 = a0[(kk + e) * lda], x1 = a1[(kk + e) * lda];
+      av[0][e] = row0 ? x0 : 0.f;
+      av[1][e] = row1 ? x1 : 0.f;
+    }
+    f4v b[NT];
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) b[tj] = ld4c(Bt + (32 * tj + r) * 64 + kk);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma(av[ti][e], b[tj][e], acc[ti][tj]);
+  }
+}
+
+template <int NT>
+__device__ inline void zero(f32x16 (&acc)[2][NT]) {
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[ti][tj][v] = 0.f;
+}
+
+// out (right-hand-side-major k-vectors, element (nu, j) at out[j * 64 + nu]) = / += acc
+template <int NT, bool ADD>
+__device__ inline void store_hat(float* __restrict__ out, const f32x16 (&acc)[2][NT]) {
+  const int l = threadIdx.x % 64;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        float* p = out + (32 * tj + l % 32) * 64 + 32 * ti + acc_row(v, l);
+        if (ADD) *p += acc[ti][tj][v]; else *p = acc[ti][tj][v];
+      }
+}
+
+// the output block of wave `g` when row blocks are dealt to the XCDs in
+// contiguous chunks (workgroups are dispatched round-robin over 8 XCDs)
+__device__ inline int64_t xcd_item(int64_t items) {
+  const int64_t nwg = gridDim.x;
+  const int64_t per = (nwg + 7) / 8;
+  const int64_t wg = static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
+  return wg * 4 + threadIdx.x / 64;  // 4 waves per workgroup, one item each
+}
+
+// ---------------------------------------------------------------- permutations
+template <typename XT>
+__global__ void mpermute_in(int64_t n, int rcur, int rp, const int32_t* __restrict__ perm, const XT* __restrict__ x,
+                            int64_t ldx, float* __restrict__ xc) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n * rp) return;
+  const int64_t p = e / rp;
+  const int j = static_cast<int>(e % rp);
+  xc[e] = j < rcur ? static_cast<float>(x[static_cast<int64_t>(j) * ldx + perm[p]]) : 0.f;
+}
+
+template <typename XT>
+__global__ void mpermute_out(int64_t n, int rcur, int rp, const int32_t* __restrict__ perm,
+                             const float* __restrict__ yc, XT* __restrict__ y, int64_t ldy, double alpha) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n * rcur) return;
+  const int64_t p = e / rcur;
+  const int j = static_cast<int>(e % rcur);
+  XT* dst = y + static_cast<int64_t>(j) * ldy + perm[p];
+  *dst = static_cast<XT>(static_cast<double>(*dst) + alpha * static_cast<double>(yc[p * rp + j]));
+}
+
+// ---------------------------------------------------------------- phases (one wave per output block)
+// x^_sigma = V_sigma^T X|sigma (Alg. 1); A(nu, p) = Vf[p][nu] (column-major view)
+template <int NT>
+__global__ __launch_bounds__(256) void mleaf_forward(int nleaves, const int32_t* __restrict__ leaves,
+                                                     const int32_t* __restrict__ cbegin,
+                                                     const int32_t* __restrict__ cend, const float* __restrict__ Vf,
+                                                     const float* __restrict__ xc, float* __restrict__ xhat) {
+  const int64_t it = xcd_item((nleaves + 3) / 4 * 4);
+  if (it >= nleaves) return;
+  constexpr int RP = 32 * NT;
+  const int32_t c = leaves[it];
+  const int64_t b0 = cbegin[c];
+  const int r = cend[c] - cbegin[c];
+  f32x16 acc[2][NT];
+  zero(acc);
+  mma_colA<NT>(Vf + b0 * 64, 64, 64, xc + b0 * RP, RP, r, acc);
+  store_hat<NT, false>(xhat + static_cast<int64_t>(c) * RP * 64, acc);
+}
+
+// x^_sigma = sum_children F^T x^_child; A(nu, nu') = ET[nu][nu'] (row-major)
+template <int NT>
+__global__ __launch_bounds__(256) void mtransfer_up(int count, const int32_t* __restrict__ list,
+                                                    const int32_t* __restrict__ child0,
+                                                    const int32_t* __restrict__ child1, const float* __restrict__ ET,
+                                                    float* __restrict__ xhat) {
+  const int64_t it = xcd_item(count);
+  if (it >= count) return;
+  constexpr int RP = 32 * NT;
+  const int32_t c = list[it];
+  f32x16 acc[2][NT];
+  zero(acc);
+  mma64_rowA<NT>(ET + static_cast<int64_t>(child0[c]) * 4096, xhat + static_cast<int64_t>(child0[c]) * RP * 64, acc);
+  mma64_rowA<NT>(ET + static_cast<int64_t>(child1[c]) * 4096, xhat + static_cast<int64_t>(child1[c]) * RP * 64, acc);
+  store_hat<NT, false>(xhat + static_cast<int64_t>(c) * RP * 64, acc);
+}
+
+// y^_tau = sum_{(tau,sigma) admissible} S_{tau sigma} x^_sigma (assigns)
+template <int NT>
+__global__ __launch_bounds__(256) void mcoupling(int nc, const int64_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ col, const float* __restrict__ S,
+                                                 const float* __restrict__ xhat, float* __restrict__ yhat) {
+  const int64_t tau = xcd_item(nc);
+  if (tau >= nc) return;
+  constexpr int RP = 32 * NT;
+  f32x16 acc[2][NT];
+  zero(acc);
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau]; b < b1; ++b)
+    mma64_rowA<NT>(S + b * 4096, xhat + static_cast<int64_t>(col[b]) * RP * 64, acc);
+  store_hat<NT, false>(yhat + tau * RP * 64, acc);
+}
+
+// y^_c += E_c y^_parent for the clusters of one level; A(nu', nu) = F[nu'][nu]
+template <int NT>
+__global__ __launch_bounds__(256) void mtransfer_down(int first, int count, const int32_t* __restrict__ parent,
+                                                      const float* __restrict__ F, float* __restrict__ yhat) {
+  const int64_t it = xcd_item(count);
+  if (it >= count) return;
+  constexpr int RP = 32 * NT;
+  const int64_t c = first + it;
+  f32x16 acc[2][NT];
+  zero(acc);
+  mma64_rowA<NT>(F + c * 4096, yhat + static_cast<int64_t>(parent[c]) * RP * 64, acc);
+  store_hat<NT, true>(yhat + c * RP * 64, acc);
+}
+
+// Y|tau = sum_{(tau,sigma) inadmissible} G|tau x sigma X|sigma + V_tau y^_tau for every leaf
+// (all leaves hold at most 64 triangles on this path)
+template <int NT>
+__global__ __launch_bounds__(256) void mnear_backward(int nleaves, const int32_t* __restrict__ leaves,
+                                                      const int32_t* __restrict__ cbegin,
+                                                      const int32_t* __restrict__ cend,
+                                                      const int64_t* __restrict__ near_ptr,
+                                                      const int32_t* __restrict__ near_col,
+                                                      const int64_t* __restrict__ panel_off,
+                                                      const float* __restrict__ N, const float* __restrict__ Vb,
+                                                      const float* __restrict__ xc, const float* __restrict__ yhat,
+                                                      float* __restrict__ yc) {
+  const int64_t it = xcd_item(nleaves);
+  if (it >= nleaves) return;
+  constexpr int RP = 32 * NT;
+  const int l = threadIdx.x % 64;
+  const int32_t tau = leaves[it];
+  const int64_t b0 = cbegin[tau];
+  const int r = cend[tau] - cbegin[tau];
+  const float* P = N + panel_off[it];
+  f32x16 acc[2][NT];
+  zero(acc);
+  int64_t colbase = 0;
+  for (int64_t bb = near_ptr[it]; bb < near_ptr[it + 1]; ++bb) {
+    const int32_t s = near_col[bb];
+    const int64_t s0 = cbegin[s];
+    const int wdt = cend[s] - cbegin[s];
+    mma_colA<NT>(P + colbase * r, r, r, xc + s0 * RP, RP, wdt, acc);
+    colbase += wdt;
+  }
+  mma_colA_Bt<NT>(Vb + b0 * 64, r, r, yhat + static_cast<int64_t>(tau) * RP * 64, acc);
+  float* out = yc + b0 * RP + l % 32;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = 32 * ti + acc_row(v, l);
+        if (i < r) out[i * RP + 32 * tj] = acc[ti][tj][v];
+      }
+}
+
+inline unsigned nblk(int64_t work, int per) {
+  const int64_t g = (work + per - 1) / per;
+  if (g > 0x7fffffff) throw Error(H2_EINVAL, "launch too large");
+  return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+template <int NT, typename XT>
+void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t ldy, double alpha, hipStream_t st) {
+  constexpr int RP = 32 * NT;
+  const Structure& S = H.S;
+  const int64_t n = S.n;
+  const int nc = S.nclusters;
+  const int nl = static_cast<int>(S.leaves.size());
+  float* xc = H.mxc.as<float>();
+  float* yc = H.myc.as<float>();
+  float* xh = H.mxhat.as<float>();
+  float* yh = H.myhat.as<float>();
+  auto waves = [](int64_t items) { return nblk((items + 3) / 4 * 4, 4) + 0u; };  // 4 waves per workgroup
+  auto grid8 = [&](int64_t items) {  // a multiple of 8 workgroups, so every XCD chunk has the same size
+    const unsigned g = waves(items);
+    return (g + 7) / 8 * 8;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+  if (H.prof) {
+    e0 = prof_event(H);
+    H2_HIP(hipEventRecord(e0, st));
+  }
+  mpermute_in<XT><<<nblk(n * RP, 256), 256, 0, st>>>(n, rcur, RP, H.perm.as<int32_t>(), x, ldx, xc);
+  mleaf_forward<NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                               H.cend.as<int32_t>(), H.Vf.as<float>(), xc, xh);
+  for (int lv = S.depth - 1; lv >= 0; --lv) {
+    const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
+    if (cnt == 0) continue;
+    mtransfer_up<NT><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
+                                                 H.child0.as<int32_t>(), H.child1.as<int32_t>(), H.ET.as<float>(), xh);
+  }
+  if (H.prof) {
+    e1 = prof_event(H);
+    H2_HIP(hipEventRecord(e1, st));
+  }
+  mcoupling<NT><<<grid8(nc), 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<float>(),
+                                           xh, yh);
+  if (H.prof) {
+    e2 = prof_event(H);
+    H2_HIP(hipEventRecord(e2, st));
+  }
+  for (int lv = 0; lv < S.depth; ++lv) {
+    const int first = S.level_ptr[lv + 1], cnt = S.level_ptr[lv + 2] - S.level_ptr[lv + 1];
+    if (cnt == 0) continue;
+    mtransfer_down<NT><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
+  }
+  if (H.prof) {
+    e3 = prof_event(H);
+    H2_HIP(hipEventRecord(e3, st));
+  }
+  mnear_backward<NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                                H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
+                                                H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
+  mpermute_out<XT><<<nblk(n * rcur, 256), 256, 0, st>>>(n, rcur, RP, H.perm.as<int32_t>(), yc, y, ldy, alpha);
+  H2_HIP(hipGetLastError());
+  if (H.prof) {
+    e4 = prof_event(H);
+    H2_HIP(hipEventRecord(e4, st));
+    prof_record(H, H2_PH_FORWARD, e0, e1);
+    prof_record(H, H2_PH_COUPLING, e1, e2);
+    prof_record(H, H2_PH_DOWN, e2, e3);
+    prof_record(H, H2_PH_NEAR, e3, e4);
+    prof_record(H, H2_PH_TOTAL, e0, e4);
+  }
+}
+
+}  // namespace
+
+bool matvec_multi_supported(const h2_handle_s& H) {
+  if (H.host_only || H.is_complex || H.P.storage != H2_F32 || H.S.k != 64) return false;
+  for (int32_t c : H.S.leaves)
+    if (H.S.cend[c] - H.S.cbegin[c] > 64) return false;  // one MFMA K-chunk per leaf
+  return true;
+}
+
+void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
+                  double alpha, hipStream_t st) {
+  const int rp = nrhs <= 32 ? 32 : 64;
+  const Structure& S = H.S;
+  const size_t need_v = static_cast<size_t>(S.n) * rp * 4, need_h = static_cast<size_t>(S.nclusters) * 64 * rp * 4;
+  if (H.mxc.bytes < need_v || H.mxhat.bytes < need_h) {
+    // workspaces grow on demand (the first many-RHS call allocates)
+    H2_HIP(hipStreamSynchronize(st));
+    H.mxc.alloc(need_v);
+    H.myc.alloc(need_v);
+    H.mxhat.alloc(need_h);
+    H.myhat.alloc(need_h);
+  }
+  const size_t es = dtype == H2_R64 ? 8 : 4;
+  for (int j0 = 0; j0 < nrhs; j0 += rp) {
+    const int rcur = std::min(rp, nrhs - j0);
+    const void* xj = static_cast<const char*>(x) + static_cast<size_t>(j0) * ldx * es;
+    void* yj = static_cast<char*>(y) + static_cast<size_t>(j0) * ldy * es;
+    if (rp == 32) {
+      if (dtype == H2_R64)
+        run_pass<1, double>(H, rcur, static_cast<const double*>(xj), ldx, static_cast<double*>(yj), ldy, alpha, st);
+      else
+        run_pass<1, float>(H, rcur, static_cast<const float*>(xj), ldx, static_cast<float*>(yj), ldy, alpha, st);
+    } else {
+      if (dtype == H2_R64)
+        run_pass<2, double>(H, rcur, static_cast<const double*>(xj), ldx, static_cast<double*>(yj), ldy, alpha, st);
+      else
+        run_pass<2, float>(H, rcur, static_cast<const float*>(xj), ldx, static_cast<float*>(yj), ldy, alpha, st);
+    }
+  }
+}
+
+}  // namespace h2

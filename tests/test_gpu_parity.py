@@ -181,3 +181,31 @@ def test_closed_forms_medium(kernel, m, name, mesh):
         assert rel(gpu_matvec(A, x), ref) <= 1e-12
     finally:
         A.close()
+
+
+@pytest.mark.parametrize("case", [("sphere", 3, 4, 16), ("sphere", 3, 4, 64), ("cube", 16, 4, 32),
+                                  ("sphere", 2, 4, 100)])
+@pytest.mark.parametrize("nrhs", [2, 17, 32, 33, 64, 70])
+def test_multi_rhs_matches_oracle(case, nrhs):
+    """Many right-hand sides (matrix-core path, FP32 storage, k = 64): every
+    column against the oracle, in the FP32 norm of each column."""
+    kind, level, m, leaf = case
+    H = oracle(kind, level, m, leaf)
+    X = I.random_vector(H.mesh.n, 11, "normal", nrhs=nrhs)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage="f32")
+    try:
+        xd = torch.tensor(X, dtype=torch.float64, device="cuda").t().contiguous().t()
+        Y0 = I.random_vector(H.mesh.n, 12, "normal", nrhs=nrhs)
+        yd = torch.tensor(Y0, dtype=torch.float64, device="cuda").t().contiguous().t()
+        A.matvec(xd, yd, alpha=0.5)
+        torch.cuda.synchronize()
+        Y = yd.cpu().numpy()
+        yd2 = torch.tensor(Y0, dtype=torch.float64, device="cuda").t().contiguous().t()
+        A.matvec(xd, yd2, alpha=0.5)
+        assert np.array_equal(yd2.cpu().numpy(), Y)                # reproducible
+    finally:
+        A.close()
+    for j in range(nrhs):
+        ref = Y0[:, j] + 0.5 * H.matvec(X[:, j])
+        scale = 0.5 * H.matvec(np.abs(X[:, j]))
+        assert np.linalg.norm(Y[:, j] - ref) <= 1e-6 * np.linalg.norm(scale), j
