@@ -69,8 +69,10 @@ extern "C" {
 #define H2_F32_SBF16 2 /* coupling matrices BF16, the rest FP32 */
 
 /* element type of user vectors */
-#define H2_R64 0 /* double */
-#define H2_R32 1 /* float */
+#define H2_R64 0  /* double */
+#define H2_R32 1  /* float */
+#define H2_C128 2 /* complex double, interleaved (re, im); Helmholtz only */
+#define H2_C64 3  /* complex float, interleaved (re, im); Helmholtz only */
 
 /* h2_matvec flags */
 #define H2_ACC_F64 1 /* accumulate in FP64 even when the matrix is stored in FP32/BF16 */
@@ -111,8 +113,10 @@ typedef struct {
  * the current HIP device).  *out receives a new handle on success. */
 int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out);
 
-/* y <- y + alpha G~ x for nrhs columns.  dtype: H2_R64 or H2_R32 for x and y.
- * flags: 0 or H2_ACC_F64.  Asynchronous on `stream`. */
+/* y <- y + alpha G~ x for nrhs columns.  dtype: H2_R64 or H2_R32 for real
+ * kernels, H2_C128 or H2_C64 (interleaved complex, ld counted in complex
+ * elements) for the Helmholtz kernel; alpha is real.  flags: 0 or H2_ACC_F64.
+ * Asynchronous on `stream`. */
 int h2_matvec(h2_handle h, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
               double alpha, int flags, void* stream);
 
@@ -138,9 +142,11 @@ typedef struct {
   double seconds;       /* wall time                                        */
 } h2_solve_info;
 
-/* Solves G~ z = b for one right-hand side (x and b FP64, device).  z is both
- * the initial guess and the result.  Returns H2_ENOTCONV if rtol was not met. */
-int h2_solve(h2_handle h, const double* b, double* z, const h2_solve_params* p,
+/* Solves G~ z = b for one right-hand side (device vectors: FP64 for real
+ * kernels, interleaved complex FP64 for Helmholtz, which requires H2_GMRES).
+ * z is both the initial guess and the result.  Returns H2_ENOTCONV if rtol was
+ * not met (z and info are still written). */
+int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p,
              h2_solve_info* info, void* stream);
 
 int h2_info(h2_handle h, h2_stats* out);

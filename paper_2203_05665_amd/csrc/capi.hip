@@ -155,7 +155,7 @@ int h2_matvec(h2_handle h, int nrhs, int dtype, const void* x, int64_t ldx, void
   });
 }
 
-int h2_solve(h2_handle h, const double* b, double* z, const h2_solve_params* p, h2_solve_info* info,
+int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p, h2_solve_info* info,
              void* stream) {
   return guarded([&]() -> int {
     if (!h || !b || !z || !p) return fail(H2_EINVAL, "NULL argument");

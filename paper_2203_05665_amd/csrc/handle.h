@@ -94,7 +94,7 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
 bool matvec_multi_supported(const h2_handle_s& H);
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
                   double alpha, hipStream_t s);
-int solve(h2_handle_s& H, const double* b, double* z, const h2_solve_params& p, h2_solve_info& info,
+int solve(h2_handle_s& H, const void* b, void* z, const h2_solve_params& p, h2_solve_info& info,
           hipStream_t s);
 hipEvent_t prof_event(h2_handle_s& H);
 void prof_record(h2_handle_s& H, int phase, hipEvent_t a, hipEvent_t b);

@@ -338,6 +338,192 @@ __global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const i
   }
 }
 
+// ---------------------------------------------------------------- complex kernels (Helmholtz)
+// S and the near field hold interleaved (re, im) entries; V and E are real (the
+// Lagrange polynomials are real), so the forward and backward transformations
+// run on the real and imaginary planes of x^, y^ with the real kernels above.
+template <typename XT, typename AT>
+__global__ void permute_in_c(int64_t n, const int32_t* __restrict__ perm, const XT* __restrict__ x,
+                             AT* __restrict__ xr, AT* __restrict__ xi) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) {
+    const int64_t t = perm[p];
+    xr[p] = static_cast<AT>(x[2 * t]);
+    xi[p] = static_cast<AT>(x[2 * t + 1]);
+  }
+}
+
+template <typename XT, typename AT>
+__global__ void permute_out_c(int64_t n, const int32_t* __restrict__ perm, const AT* __restrict__ yr,
+                              const AT* __restrict__ yi, XT* __restrict__ y, double alpha) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) {
+    const int64_t t = perm[p];
+    y[2 * t] = static_cast<XT>(static_cast<double>(y[2 * t]) + alpha * static_cast<double>(yr[p]));
+    y[2 * t + 1] = static_cast<XT>(static_cast<double>(y[2 * t + 1]) + alpha * static_cast<double>(yi[p]));
+  }
+}
+
+// k = 64: one workgroup per row cluster, 16-byte loads of interleaved complex S
+template <typename SST, typename AT>
+__global__ __launch_bounds__(256) void coupling64c(int nc, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col, const SST* __restrict__ S,
+                                                   const AT* __restrict__ xr, const AT* __restrict__ xi,
+                                                   AT* __restrict__ yr, AT* __restrict__ yi) {
+  constexpr int VEC = Vec16<SST>::N;
+  constexpr int CPV = VEC / 2;  // complex entries per 16-byte load
+  constexpr int LPR = 64 / CPV;
+  constexpr int RPP = 256 / LPR;
+  constexpr int NP = 64 / RPP;
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int t = threadIdx.x;
+  const int lr = t % LPR, r0 = t / LPR;
+  AT ar[NP], ai[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) ar[j] = ai[j] = 0;
+  for (int64_t b = ptr[tau]; b < ptr[tau + 1]; ++b) {
+    const int64_t s = col[b];
+    AT vr[CPV], vi[CPV];
+#pragma unroll
+    for (int c = 0; c < CPV; ++c) {
+      vr[c] = xr[s * 64 + lr * CPV + c];
+      vi[c] = xi[s * 64 + lr * CPV + c];
+    }
+    const SST* Sb = S + b * 8192 + lr * VEC;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      AT sv[VEC];
+      Vec16<SST>::load(Sb + (r0 + j * RPP) * 128, sv);
+#pragma unroll
+      for (int c = 0; c < CPV; ++c) {
+        ar[j] += sv[2 * c] * vr[c] - sv[2 * c + 1] * vi[c];
+        ai[j] += sv[2 * c] * vi[c] + sv[2 * c + 1] * vr[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) {
+      ar[j] += __shfl_xor(ar[j], off);
+      ai[j] += __shfl_xor(ai[j], off);
+    }
+  if (lr == 0) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      yr[static_cast<int64_t>(tau) * 64 + r0 + j * RPP] = ar[j];
+      yi[static_cast<int64_t>(tau) * 64 + r0 + j * RPP] = ai[j];
+    }
+  }
+}
+
+template <typename SST, typename AT>
+__global__ __launch_bounds__(256) void coupling_anyc(int nc, int k, const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col, const SST* __restrict__ S,
+                                                     const AT* __restrict__ xr, const AT* __restrict__ xi,
+                                                     AT* __restrict__ yr, AT* __restrict__ yi) {
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  for (int nu = threadIdx.x; nu < k; nu += blockDim.x) {
+    AT ar = 0, ai = 0;
+    for (int64_t b = ptr[tau]; b < ptr[tau + 1]; ++b) {
+      const SST* Sb = S + 2 * (b * kk + static_cast<int64_t>(nu) * k);
+      const int64_t s = col[b];
+      for (int mu = 0; mu < k; ++mu) {
+        const AT sr = ld<SST, AT>(Sb + 2 * mu), si = ld<SST, AT>(Sb + 2 * mu + 1);
+        ar += sr * xr[s * k + mu] - si * xi[s * k + mu];
+        ai += sr * xi[s * k + mu] + si * xr[s * k + mu];
+      }
+    }
+    yr[static_cast<int64_t>(tau) * k + nu] = ar;
+    yi[static_cast<int64_t>(tau) * k + nu] = ai;
+  }
+}
+
+// near field (complex panels, lane = row) + leaf backward (real V times both planes)
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void near_backward_c(int nleaves, int k, const int32_t* __restrict__ leaves,
+                                                       const int32_t* __restrict__ cbegin,
+                                                       const int32_t* __restrict__ cend,
+                                                       const int64_t* __restrict__ near_ptr,
+                                                       const int32_t* __restrict__ near_col,
+                                                       const int64_t* __restrict__ panel_off,
+                                                       const ST* __restrict__ N, const ST* __restrict__ Vb,
+                                                       const AT* __restrict__ xr, const AT* __restrict__ xi,
+                                                       const AT* __restrict__ yhr, const AT* __restrict__ yhi,
+                                                       AT* __restrict__ ycr, AT* __restrict__ yci) {
+  __shared__ AT part[2][4][64];
+  const int l = blockIdx.x;
+  if (l >= nleaves) return;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int32_t tau = leaves[l];
+  const int64_t b0 = cbegin[tau];
+  const int r = cend[tau] - cbegin[tau];
+  const ST* P = N + 2 * panel_off[l];
+  const ST* Vl = Vb + b0 * k;
+  const int64_t bfirst = near_ptr[l], blast = near_ptr[l + 1];
+  for (int i0 = 0; i0 < r; i0 += 64) {
+    const int i = i0 + lane;
+    const int is = i < r ? i : r - 1;
+    AT accr = 0, acci = 0;
+    int64_t colbase = 0;
+    for (int64_t bb = bfirst; bb < blast; ++bb) {
+      const int32_t s = near_col[bb];
+      const int64_t s0 = cbegin[s];
+      const int w = cend[s] - cbegin[s];
+      if (((bb - bfirst) & 3) == wave) {
+        for (int j0 = 0; j0 < w; j0 += 64) {
+          const AT vr = j0 + lane < w ? xr[s0 + j0 + lane] : AT(0);
+          const AT vi = j0 + lane < w ? xi[s0 + j0 + lane] : AT(0);
+          const ST* Pc = P + 2 * ((colbase + j0) * r + is);
+          const int cnt = min(64, w - j0);
+          int j = 0;
+          for (; j + 4 <= cnt; j += 4) {
+            AT nr[4], ni[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              nr[u] = ld<ST, AT>(Pc + 2 * static_cast<int64_t>(j + u) * r);
+              ni[u] = ld<ST, AT>(Pc + 2 * static_cast<int64_t>(j + u) * r + 1);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const AT br = bcast(vr, j + u), bi = bcast(vi, j + u);
+              accr += nr[u] * br - ni[u] * bi;
+              acci += nr[u] * bi + ni[u] * br;
+            }
+          }
+          for (; j < cnt; ++j) {
+            const AT nr = ld<ST, AT>(Pc + 2 * static_cast<int64_t>(j) * r);
+            const AT ni = ld<ST, AT>(Pc + 2 * static_cast<int64_t>(j) * r + 1);
+            const AT br = bcast(vr, j), bi = bcast(vi, j);
+            accr += nr * br - ni * bi;
+            acci += nr * bi + ni * br;
+          }
+        }
+      }
+      colbase += w;
+    }
+    const int kq = (k + 3) / 4;
+    const int n0 = wave * kq, n1 = min(k, n0 + kq);
+    for (int q0 = n0; q0 < n1; q0 += 64) {
+      const AT yr = q0 + lane < n1 ? yhr[static_cast<int64_t>(tau) * k + q0 + lane] : AT(0);
+      const AT yi = q0 + lane < n1 ? yhi[static_cast<int64_t>(tau) * k + q0 + lane] : AT(0);
+      accr = stream_dot<ST, AT>(Vl + static_cast<int64_t>(q0) * r + is, r, min(64, n1 - q0), yr, accr);
+      acci = stream_dot<ST, AT>(Vl + static_cast<int64_t>(q0) * r + is, r, min(64, n1 - q0), yi, acci);
+    }
+    part[0][wave][lane] = accr;
+    part[1][wave][lane] = acci;
+    __syncthreads();
+    if (wave == 0 && i < r) {
+      ycr[b0 + i] = (part[0][0][lane] + part[0][1][lane]) + (part[0][2][lane] + part[0][3][lane]);
+      yci[b0 + i] = (part[1][0][lane] + part[1][1][lane]) + (part[1][2][lane] + part[1][3][lane]);
+    }
+    __syncthreads();
+  }
+}
+
 inline unsigned blocks_for(int64_t work, int per) {
   const int64_t g = (work + per - 1) / per;
   if (g > 0x7fffffff) throw Error(H2_EINVAL, "launch too large");
@@ -419,18 +605,119 @@ void matvec_x(h2_handle_s& H, int dtype, const void* x, void* y, double alpha, h
     matvec_typed<SST, ST, AT, float>(H, static_cast<const float*>(x), static_cast<float*>(y), alpha, st);
 }
 
+template <typename SST, typename ST, typename AT, typename XT>
+void matvec_complex(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t st) {
+  const Structure& S = H.S;
+  const int k = S.k;
+  const int64_t n = S.n;
+  const int nc = S.nclusters;
+  const int nl = static_cast<int>(S.leaves.size());
+  const int64_t nh = static_cast<int64_t>(nc) * k;
+  AT* xr = H.xc.as<AT>();
+  AT* xi = xr + n;
+  AT* ycr = H.yc.as<AT>();
+  AT* yci = ycr + n;
+  AT* xhr = H.xhat.as<AT>();
+  AT* xhi = xhr + nh;
+  AT* yhr = H.yhat.as<AT>();
+  AT* yhi = yhr + nh;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+  if (H.prof) {
+    e0 = prof_event(H);
+    H2_HIP(hipEventRecord(e0, st));
+  }
+  permute_in_c<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), x, xr, xi);
+  AT* planes_x[2] = {xr, xi};
+  AT* planes_h[2] = {xhr, xhi};
+  for (int pl = 0; pl < 2; ++pl) {
+    leaf_forward<ST, AT><<<blocks_for(nl, 4), 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                             H.cend.as<int32_t>(), H.Vf.as<ST>(), planes_x[pl],
+                                                             planes_h[pl]);
+    for (int l = S.depth - 1; l >= 0; --l) {
+      const int cnt = static_cast<int>(H.up_ptr[l + 1] - H.up_ptr[l]);
+      if (cnt == 0) continue;
+      transfer_up<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, k, H.up_list.as<int32_t>() + H.up_ptr[l],
+                                                               H.child0.as<int32_t>(), H.child1.as<int32_t>(),
+                                                               H.F.as<ST>(), planes_h[pl]);
+    }
+  }
+  if (H.prof) {
+    e1 = prof_event(H);
+    H2_HIP(hipEventRecord(e1, st));
+  }
+  if (k == 64)
+    coupling64c<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
+                                            H.Smat.as<SST>(), xhr, xhi, yhr, yhi);
+  else
+    coupling_anyc<SST, AT><<<nc, 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
+                                              H.Smat.as<SST>(), xhr, xhi, yhr, yhi);
+  if (H.prof) {
+    e2 = prof_event(H);
+    H2_HIP(hipEventRecord(e2, st));
+  }
+  AT* planes_y[2] = {yhr, yhi};
+  for (int pl = 0; pl < 2; ++pl)
+    for (int l = 0; l < S.depth; ++l) {
+      const int first = S.level_ptr[l + 1], cnt = S.level_ptr[l + 2] - S.level_ptr[l + 1];
+      if (cnt == 0) continue;
+      transfer_down<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, k, H.parent.as<int32_t>(),
+                                                                 H.ET.as<ST>(), planes_y[pl]);
+    }
+  if (H.prof) {
+    e3 = prof_event(H);
+    H2_HIP(hipEventRecord(e3, st));
+  }
+  near_backward_c<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                              H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                              H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
+                                              H.Vb.as<ST>(), xr, xi, yhr, yhi, ycr, yci);
+  permute_out_c<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), ycr, yci, y, alpha);
+  H2_HIP(hipGetLastError());
+  if (H.prof) {
+    e4 = prof_event(H);
+    H2_HIP(hipEventRecord(e4, st));
+    prof_record(H, H2_PH_FORWARD, e0, e1);
+    prof_record(H, H2_PH_COUPLING, e1, e2);
+    prof_record(H, H2_PH_DOWN, e2, e3);
+    prof_record(H, H2_PH_NEAR, e3, e4);
+    prof_record(H, H2_PH_TOTAL, e0, e4);
+  }
+}
+
+template <typename SST, typename ST, typename AT>
+void matvec_cx(h2_handle_s& H, int dtype, const void* x, void* y, double alpha, hipStream_t st) {
+  if (dtype == H2_C128)
+    matvec_complex<SST, ST, AT, double>(H, static_cast<const double*>(x), static_cast<double*>(y), alpha, st);
+  else
+    matvec_complex<SST, ST, AT, float>(H, static_cast<const float*>(x), static_cast<float*>(y), alpha, st);
+}
+
 }  // namespace
 
 void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy, double alpha,
             int flags, hipStream_t st) {
   if (H.host_only) throw Error(H2_EINVAL, "handle was built with H2_HOST_ONLY");
-  if (H.is_complex) throw Error(H2_EINVAL, "complex kernels are applied with h2_matvec_complex");
   if (nrhs < 0) throw Error(H2_EINVAL, "nrhs must be >= 0");
-  if (dtype != H2_R64 && dtype != H2_R32) throw Error(H2_EINVAL, "dtype must be H2_R64 or H2_R32");
+  const bool cx = dtype == H2_C128 || dtype == H2_C64;
+  if (dtype != H2_R64 && dtype != H2_R32 && !cx) throw Error(H2_EINVAL, "unknown dtype");
+  if (cx != H.is_complex)
+    throw Error(H2_EINVAL, H.is_complex ? "the Helmholtz matrix needs complex vectors (H2_C128/H2_C64)"
+                                        : "complex vectors need the Helmholtz kernel");
   if (nrhs > 0 && (x == nullptr || y == nullptr)) throw Error(H2_EINVAL, "x and y must not be NULL");
   if (ldx < H.S.n || ldy < H.S.n) throw Error(H2_EINVAL, "leading dimension smaller than n");
-  const size_t es = dtype == H2_R64 ? 8 : 4;
   const bool acc64 = (flags & H2_ACC_F64) != 0;
+  if (cx) {
+    const size_t es = dtype == H2_C128 ? 16 : 8;
+    for (int j = 0; j < nrhs; ++j) {
+      const void* xj = static_cast<const char*>(x) + static_cast<size_t>(j) * ldx * es;
+      void* yj = static_cast<char*>(y) + static_cast<size_t>(j) * ldy * es;
+      if (H.P.storage == H2_F64) matvec_cx<double, double, double>(H, dtype, xj, yj, alpha, st);
+      else if (acc64) matvec_cx<float, float, double>(H, dtype, xj, yj, alpha, st);
+      else matvec_cx<float, float, float>(H, dtype, xj, yj, alpha, st);
+    }
+    return;
+  }
+  const size_t es = dtype == H2_R64 ? 8 : 4;
   if (nrhs >= 2 && !acc64 && matvec_multi_supported(H)) {
     matvec_multi(H, nrhs, dtype, x, ldx, y, ldy, alpha, st);
     return;

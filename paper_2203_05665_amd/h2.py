@@ -20,7 +20,7 @@ LIBPATH = os.path.join(HERE, "libh2mi355x.so")
 H2_OK, H2_EINVAL, H2_ENOMEM, H2_EHIP, H2_ENOTCONV, H2_EINTERNAL = 0, -1, -2, -3, -4, -5
 H2_LAPLACE, H2_HELMHOLTZ, H2_TEST_ONE, H2_TEST_BILINEAR, H2_TEST_QUADRATIC = 0, 1, 2, 3, 4
 H2_F64, H2_F32, H2_F32_SBF16 = 0, 1, 2
-H2_R64, H2_R32 = 0, 1
+H2_R64, H2_R32, H2_C128, H2_C64 = 0, 1, 2, 3
 H2_ACC_F64 = 1
 H2_HOST_ONLY = 1
 H2_CG, H2_GMRES = 0, 1
@@ -131,8 +131,9 @@ def _stream(stream):
 def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
     """y <- y + alpha G~ x for torch CUDA tensors x, y (n or n x nrhs, Fortran order)."""
     import torch
-    if x.dtype != y.dtype or x.dtype not in (torch.float64, torch.float32):
-        raise TypeError("x and y must both be float64 or both float32")
+    dtypes = {torch.float64: H2_R64, torch.float32: H2_R32, torch.complex128: H2_C128, torch.complex64: H2_C64}
+    if x.dtype != y.dtype or x.dtype not in dtypes:
+        raise TypeError("x and y must have the same dtype: float64, float32, complex128 or complex64")
     if not (x.is_cuda and y.is_cuda):
         raise TypeError("x and y must be device tensors")
     nrhs = 1 if x.dim() == 1 else x.shape[1]
@@ -141,7 +142,7 @@ def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
     ldy = y.stride(1) if y.dim() == 2 else n
     if x.stride(0) != 1 or y.stride(0) != 1:
         raise ValueError("columns must be contiguous")
-    dt = H2_R64 if x.dtype == torch.float64 else H2_R32
+    dt = dtypes[x.dtype]
     _check(lib().h2_matvec(h, nrhs, dt, x.data_ptr(), ldx, y.data_ptr(), ldy, float(alpha),
                            H2_ACC_F64 if acc64 else 0, _stream(stream)))
     return y
@@ -149,7 +150,12 @@ def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
 
 def h2_solve(h, b, z, method="cg", rtol=1e-8, maxit=1000, restart=50, refine=False, inner_rtol=1e-4,
              stream=None, check=True):
-    """Solves G~ z = b (float64 device tensors); z holds the initial guess and the result."""
+    """Solves G~ z = b (float64, or complex128 for Helmholtz, device tensors); z holds
+    the initial guess and the result."""
+    import torch
+    want = torch.complex128 if b.is_complex() else torch.float64
+    if b.dtype != want or z.dtype != want or not (b.is_cuda and z.is_cuda):
+        raise TypeError("b and z must be float64 (complex128 for Helmholtz) device tensors")
     p = h2_solve_params(H2_CG if method == "cg" else H2_GMRES, int(restart), int(maxit), float(rtol),
                         1 if refine else 0, float(inner_rtol))
     info = h2_solve_info()
