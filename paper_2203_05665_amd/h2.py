@@ -138,9 +138,12 @@ def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
         raise TypeError("x and y must be device tensors")
     nrhs = 1 if x.dim() == 1 else x.shape[1]
     n = x.shape[0]
-    ldx = x.stride(1) if x.dim() == 2 else n
-    ldy = y.stride(1) if y.dim() == 2 else n
-    if x.stride(0) != 1 or y.stride(0) != 1:
+    if x.shape != y.shape:
+        raise ValueError("x and y must have the same shape")
+    # a single column may carry any stride in its second dimension
+    ldx = x.stride(1) if x.dim() == 2 and nrhs > 1 else n
+    ldy = y.stride(1) if y.dim() == 2 and nrhs > 1 else n
+    if n > 1 and (x.stride(0) != 1 or y.stride(0) != 1):
         raise ValueError("columns must be contiguous")
     dt = dtypes[x.dtype]
     _check(lib().h2_matvec(h, nrhs, dt, x.data_ptr(), ldx, y.data_ptr(), ldy, float(alpha),

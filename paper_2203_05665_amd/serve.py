@@ -1,0 +1,569 @@
+"""Continuous-batching solve service over HBM-resident H^2 matrices.
+
+Requests ask for G~ z = b on a registered mesh (Laplace, or Helmholtz with a
+wave number) with 1..R right-hand sides.  The engine
+
+* keeps the H^2 structures resident on the device and admits a structure by its
+  footprint against a memory budget, evicting idle structures (least recently
+  used first) when a new one does not fit;
+* admits requests into a bounded number of slots as slots and memory free up;
+* runs every admitted request as a step-wise Krylov iteration (CG for the
+  symmetric positive definite Laplace matrix, restarted GMRES for Helmholtz),
+  optionally wrapped in FP64 iterative refinement for FP32 storage;
+* on every scheduler tick gathers the pending matrix products of all active
+  requests, groups them by structure, and issues ONE many-right-hand-side
+  product per group (h2_matvec with all the groups' columns) on that
+  structure's stream, so requests on different meshes overlap on the device and
+  requests on the same mesh share one pass over its matrix data;
+* reports per-request latency (arrival to result), p50/p99 and throughput.
+
+The product y <- y + G~ X is the library's (libh2mi355x.so through the ctypes
+binding); the Krylov vector algebra of each request (inner products, vector
+updates, Givens rotations) runs as FP64 tensor operations on the request's
+stream.  A backend object supplies the products, so the scheduler can also be
+driven by a CPU backend in tests.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Tuple
+
+import numpy as np
+
+# ---------------------------------------------------------------------------- backends
+
+
+class GPUBackend:
+    """Builds H^2 matrices with the HIP library; vectors are CUDA tensors."""
+
+    def __init__(self, order=4, leaf=64, eta=0.5, storage="f32", device="cuda"):
+        import torch
+        from . import h2
+        self.torch, self.h2 = torch, h2
+        self.order, self.leaf, self.eta, self.storage = order, leaf, eta, storage
+        self.device = torch.device(device)
+
+    def estimate(self, V, T, kernel, kappa):
+        """Device bytes of the structure, from a host-only build of its trees."""
+        h2 = self.h2
+        h = h2.build_h2(V, T, kernel=kernel, kappa=kappa, order=self.order, leaf=self.leaf, eta=self.eta,
+                        storage=self.storage, host_only=True)
+        try:
+            i = h2.h2_info(h)
+        finally:
+            h2.h2_free(h)
+        cw = 2 if kernel == "helmholtz" else 1
+        vb = 8 if self.storage == "f64" else 4
+        sb = {"f64": 8, "f32": 4, "f32_sbf16": 2}[self.storage]
+        k, n, nc = i["k"], i["n"], i["nclusters"]
+        data = cw * (sb * k * k * i["n_adm"] + vb * i["near_entries"]) + vb * (4 * n * k + 2 * k * k * nc)
+        work = 2 * 8 * cw * (n + nc * k) + 4 * 64 * (2 * n + 2 * nc * k)   # one- and many-RHS workspaces
+        return int(data + work)
+
+    def build(self, V, T, kernel, kappa):
+        A = self.h2.H2Matrix(V, T, kernel=kernel, kappa=kappa, order=self.order, leaf=self.leaf, eta=self.eta,
+                             storage=self.storage)
+        return A, self.estimate(V, T, kernel, kappa)
+
+    def matvec(self, A, X, Y, acc64, stream):
+        """Y <- Y + G~ X (X, Y: n x R Fortran-ordered device tensors)."""
+        A.matvec(X, Y, alpha=1.0, acc64=acc64, stream=stream.cuda_stream if stream is not None else None)
+
+    def free(self, A):
+        A.close()
+
+    def new_stream(self):
+        return self.torch.cuda.Stream(device=self.device)
+
+    def refine(self):
+        return self.storage != "f64"
+
+
+# ---------------------------------------------------------------------------- Krylov state machines
+
+
+class _CG:
+    """Conjugate gradients for all columns of B at once (independent columns)."""
+
+    def __init__(self, torch, B, tol, maxit):
+        self.t = torch
+        self.B = B
+        self.X = torch.zeros_like(B)
+        self.R = B.clone()
+        self.P = B.clone()
+        self.rr = (B * B).sum(0)
+        self.nb = self.t.sqrt(self.rr)
+        self.tol, self.maxit, self.it = tol, maxit, 0
+        self.done = bool((self.nb == 0).all())
+
+    def operand(self):
+        return self.P
+
+    def advance(self, Q):
+        t = self.t
+        pq = (self.P * Q).sum(0)
+        alpha = t.where(pq > 0, self.rr / t.where(pq > 0, pq, t.ones_like(pq)), t.zeros_like(pq))
+        self.X += alpha * self.P
+        self.R -= alpha * Q
+        rr2 = (self.R * self.R).sum(0)
+        beta = t.where(self.rr > 0, rr2 / t.where(self.rr > 0, self.rr, t.ones_like(self.rr)), t.zeros_like(rr2))
+        self.P = self.R + beta * self.P
+        self.rr = rr2
+        self.it += 1
+
+    def relres(self):
+        t = self.t
+        return t.sqrt(self.rr) / t.where(self.nb > 0, self.nb, t.ones_like(self.nb))
+
+    def solution(self):
+        return self.X
+
+
+class _GMRES:
+    """Restarted GMRES for all columns of B at once (independent Arnoldi
+    processes advanced in lockstep; classical Gram-Schmidt twice; complex
+    Givens rotations), FP64 / complex128.
+
+    phase "arnoldi": the next product is A q_j;  phase "residual": the next
+    product is A X (true residual at the end of a restart cycle);  phase
+    "converged": every column meets the tolerance."""
+
+    def __init__(self, torch, B, tol, maxit, restart):
+        self.t = torch
+        self.B = B
+        self.m = restart
+        self.tol, self.maxit, self.it = tol, maxit, 0
+        self.X = torch.zeros_like(B)
+        n, r = B.shape
+        self.nb = torch.linalg.vector_norm(B, dim=0)
+        self.Q = torch.zeros((self.m + 1, n, r), dtype=B.dtype, device=B.device)
+        cdt = torch.complex128
+        self.H = torch.zeros((self.m + 1, self.m, r), dtype=cdt, device=B.device)
+        self.cs = torch.zeros((self.m, r), dtype=cdt, device=B.device)
+        self.sn = torch.zeros((self.m, r), dtype=cdt, device=B.device)
+        self.g = torch.zeros((self.m + 1, r), dtype=cdt, device=B.device)
+        self.j = 0
+        self._rel = torch.ones(r, dtype=torch.float64, device=B.device)
+        self._start(B)                       # X = 0: the residual is B itself
+
+    def _start(self, R):
+        t = self.t
+        beta = t.linalg.vector_norm(R, dim=0)
+        self._rel = beta / t.where(self.nb > 0, self.nb, t.ones_like(self.nb))
+        self.Q.zero_()
+        self.H.zero_()
+        self.g.zero_()
+        self.Q[0] = R / t.where(beta > 0, beta, t.ones_like(beta)).to(R.dtype)
+        self.g[0] = beta.to(self.g.dtype)
+        self.j = 0
+        self.phase = "arnoldi"
+
+    def operand(self):
+        return self.X if self.phase == "residual" else self.Q[self.j]
+
+    def _cdot(self, a, b):  # column-wise conj(a).b
+        return (a.conj() * b).sum(0) if a.is_complex() else (a * b).sum(0)
+
+    def advance(self, Y):
+        t = self.t
+        if self.phase == "residual":
+            self._start(self.B - Y)
+            return
+        j = self.j
+        W = Y.clone()
+        hcol = t.zeros((self.m + 1, W.shape[1]), dtype=self.H.dtype, device=W.device)
+        Qj = self.Q[: j + 1]
+        for _ in range(2):                                                  # classical Gram-Schmidt, twice
+            h = t.einsum("inr,nr->ir", Qj.conj() if W.is_complex() else Qj, W)  # (j+1, r)
+            W = W - t.einsum("ir,inr->nr", h, Qj)
+            hcol[: j + 1] += h.to(hcol.dtype)
+        hn = t.linalg.vector_norm(W, dim=0)
+        hcol[j + 1] = hn.to(hcol.dtype)
+        self.Q[j + 1] = W / t.where(hn > 0, hn, t.ones_like(hn)).to(W.dtype)
+        for i in range(j):
+            tmp = self.cs[i] * hcol[i] + self.sn[i] * hcol[i + 1]
+            hcol[i + 1] = -self.sn[i].conj() * hcol[i] + self.cs[i] * hcol[i + 1]
+            hcol[i] = tmp
+        a, c = hcol[j], hcol[j + 1]
+        absa = a.abs()
+        den = t.sqrt(absa ** 2 + c.abs() ** 2)
+        safe = absa > 0
+        one_r = t.ones_like(absa)
+        self.cs[j] = t.where(safe, (absa / t.where(den > 0, den, one_r)).to(a.dtype), t.zeros_like(a))
+        unit = t.where(safe, a / t.where(safe, absa, one_r).to(a.dtype), t.ones_like(a))
+        self.sn[j] = t.where(safe, unit * c.conj() / t.where(den > 0, den, one_r).to(a.dtype), t.ones_like(a))
+        hcol[j] = self.cs[j] * a + self.sn[j] * c
+        hcol[j + 1] = 0
+        self.g[j + 1] = -self.sn[j].conj() * self.g[j]
+        self.g[j] = self.cs[j] * self.g[j]
+        self.H[:, j] = hcol
+        self.it += 1
+        self.j += 1
+        self._rel = self.g[self.j].abs() / t.where(self.nb > 0, self.nb, t.ones_like(self.nb))
+
+    def close_cycle(self):
+        """Solve the small triangular systems, update X, and ask for the true residual."""
+        t = self.t
+        k = self.j
+        if k > 0:
+            Hk = self.H[:k, :k].permute(2, 0, 1)                      # (r, k, k)
+            gk = self.g[:k].permute(1, 0).unsqueeze(-1)               # (r, k, 1)
+            diag = t.diagonal(Hk, dim1=1, dim2=2)
+            Hk = Hk + t.diag_embed(t.where(diag == 0, t.ones_like(diag), t.zeros_like(diag)))
+            y = t.linalg.solve_triangular(Hk, gk, upper=True).squeeze(-1).permute(1, 0)   # (k, r)
+            self.X += t.einsum("kr,knr->nr", y if self.X.is_complex() else y.real, self.Q[:k])
+        self.phase = "residual"
+        self.j = 0
+
+    def fresh(self):
+        """True right after a (re)start: _rel is the true relative residual."""
+        return self.phase == "arnoldi" and self.j == 0
+
+    def step_done(self):
+        """After an Arnoldi step: close the cycle when it is full, when the residual
+        estimate meets the tolerance, or when the iteration budget is spent (the
+        next product then yields the true residual)."""
+        if self.phase == "arnoldi" and self.j > 0:
+            if self.j >= self.m or float(self._rel.max()) <= self.tol or self.it >= self.maxit:
+                self.close_cycle()
+
+    def relres(self):
+        return self._rel
+
+    def solution(self):
+        return self.X
+
+
+# ---------------------------------------------------------------------------- requests
+
+
+@dataclass
+class Request:
+    rid: int
+    mesh: str
+    kernel: str
+    kappa: float
+    b: object                      # n x r tensor (float64 or complex128) on the backend device
+    rtol: float = 1e-8
+    arrival: float = 0.0
+    maxit: int = 1000
+    restart: int = 30
+    inner_rtol: float = 1e-4
+    # runtime
+    status: str = "queued"         # queued, active, done, not_converged, failed
+    error: str = ""
+    start: float = 0.0
+    finish: float = 0.0
+    iterations: int = 0
+    products: int = 0
+    result: object = None
+    rel_residual: float = float("nan")
+    _solver: object = None
+    _phase: str = "outer"          # outer (FP64 residual) or inner (Krylov)
+    _z: object = None
+    _resid: object = None
+    _outer_R: object = None
+
+    @property
+    def key(self):
+        return (self.mesh, self.kernel, float(self.kappa))
+
+    @property
+    def latency(self):
+        return self.finish - self.arrival
+
+
+@dataclass
+class _Resident:
+    obj: object
+    nbytes: int
+    stream: object
+    active: int = 0
+    last_used: float = 0.0
+
+
+class H2Server:
+    """Continuous-batching scheduler (see module docstring)."""
+
+    def __init__(self, backend, mem_budget: float, max_active: int = 32, clock: Callable[[], float] = time.perf_counter):
+        self.be = backend
+        self.t = __import__("torch")
+        self.budget = float(mem_budget)
+        self.max_active = int(max_active)
+        self.clock = clock
+        self.meshes: Dict[str, Tuple[np.ndarray, np.ndarray]] = {}
+        self.resident: Dict[tuple, _Resident] = {}
+        self.queue: List[Request] = []
+        self.active: List[Request] = []
+        self.finished: List[Request] = []
+        self._next = 0
+        self._est: Dict[tuple, int] = {}
+        self.ticks = 0
+        self.batched_products = 0
+
+    # -- registry ---------------------------------------------------------------------
+    def register_mesh(self, name: str, vertices, triangles):
+        self.meshes[name] = (np.asarray(vertices, np.float64), np.asarray(triangles, np.int32))
+
+    def submit(self, mesh: str, b, kernel="laplace", kappa=0.0, rtol=1e-8, arrival=None, **kw) -> Request:
+        t = self.t
+        b = t.as_tensor(b)
+        if b.dim() == 1:
+            b = b[:, None]
+        cx = kernel == "helmholtz"
+        b = b.to(device=self.be.device, dtype=t.complex128 if cx else t.float64)
+        req = Request(self._next, mesh, kernel, float(kappa), b, rtol=rtol,
+                      arrival=self.clock() if arrival is None else arrival, **kw)
+        self._next += 1
+        if mesh not in self.meshes:
+            req.status, req.error = "failed", "unknown mesh %r" % mesh
+            self.finished.append(req)
+        elif b.shape[0] != self.meshes[mesh][1].shape[0]:
+            req.status, req.error = "failed", "right-hand side has %d rows, mesh has %d triangles" % (
+                b.shape[0], self.meshes[mesh][1].shape[0])
+            self.finished.append(req)
+        elif not bool(t.isfinite(t.view_as_real(b) if cx else b).all()):
+            req.status, req.error = "failed", "right-hand side is not finite"
+            self.finished.append(req)
+        else:
+            self.queue.append(req)
+        return req
+
+    # -- memory -----------------------------------------------------------------------
+    def used_bytes(self) -> int:
+        return sum(r.nbytes for r in self.resident.values()) + sum(self._req_bytes(q) for q in self.active)
+
+    def _req_bytes(self, q: Request) -> int:
+        n, r = q.b.shape
+        es = q.b.element_size()
+        nvec = (q.restart + 6) if q.kernel == "helmholtz" else 8
+        return int(n * r * es * nvec)
+
+    def _footprint(self, key) -> int:
+        if key not in self._est:
+            mesh, kernel, kappa = key
+            V, T = self.meshes[mesh]
+            self._est[key] = int(self.be.estimate(V, T, kernel, kappa))
+        return self._est[key]
+
+    def _make_resident(self, key, extra) -> Optional[_Resident]:
+        """The resident structure for `key`, building it if the budget allows after
+        evicting idle structures (least recently used first); None = wait."""
+        if key in self.resident:
+            return self.resident[key]
+        nbytes = self._footprint(key)
+        while self.used_bytes() + nbytes + extra > self.budget:
+            idle = [(r.last_used, k) for k, r in self.resident.items() if r.active == 0]
+            if not idle:
+                return None
+            _, victim = min(idle)
+            self.be.free(self.resident.pop(victim).obj)
+        mesh, kernel, kappa = key
+        V, T = self.meshes[mesh]
+        obj, real = self.be.build(V, T, kernel, kappa)
+        res = _Resident(obj, int(real), self.be.new_stream(), 0, self.clock())
+        self.resident[key] = res
+        return res
+
+    # -- scheduling ---------------------------------------------------------------------
+    def _admit(self, now):
+        keep = []
+        for q in self.queue:
+            if q.arrival > now or len(self.active) >= self.max_active:
+                keep.append(q)
+                continue
+            try:
+                need = self._req_bytes(q)
+                if self._footprint(q.key) + need > self.budget:
+                    q.status, q.error, q.finish = "failed", "does not fit the memory budget", now
+                    self.finished.append(q)
+                    continue
+                res = self._make_resident(q.key, need)
+            except Exception as e:  # a failed build fails the request, not the server
+                q.status, q.error, q.finish = "failed", "build failed: %s" % e, self.clock()
+                self.finished.append(q)
+                continue
+            if res is None or self.used_bytes() + need > self.budget:
+                keep.append(q)
+                continue
+            res.active += 1
+            q.status, q.start = "active", now
+            q._z = self.t.zeros_like(q.b)
+            q._phase = "outer" if self._refine(q) else "inner"
+            if q._phase == "inner":
+                q._solver = self._new_solver(q, q.b, q.rtol)
+            self.active.append(q)
+        self.queue = keep
+
+    def _refine(self, q):
+        return self.be.refine()
+
+    def _new_solver(self, q, rhs, tol):
+        left = max(1, q.maxit - q.iterations)
+        if q.kernel == "helmholtz":
+            return _GMRES(self.t, rhs, tol, left, q.restart)
+        return _CG(self.t, rhs, tol, left)
+
+    def _operand(self, q) -> Tuple[object, bool]:
+        """The vector block whose product this request needs next, and whether the
+        product accumulates in FP64 (outer residual of the refinement)."""
+        if q._phase == "outer":
+            return q._z, True
+        return q._solver.operand(), False
+
+    def tick(self) -> int:
+        """Admit arrivals, run one batched product per (structure, accumulation)
+        group, advance every active request.  Returns the number of products."""
+        t = self.t
+        now = self.clock()
+        self._admit(now)
+        if not self.active:
+            return 0
+        groups: Dict[tuple, List[Request]] = {}
+        for q in self.active:
+            X, acc64 = self._operand(q)
+            groups.setdefault((q.key, acc64), []).append(q)
+        outs = {}
+        for (key, acc64), reqs in groups.items():
+            res = self.resident[key]
+            res.last_used = now
+            stream = res.stream
+            ctx = t.cuda.stream(stream) if stream is not None else _nullcontext()
+            with ctx:
+                if stream is not None:       # right-hand sides were made on the submitting stream
+                    stream.wait_stream(t.cuda.default_stream(stream.device))
+                ops = [self._operand(q)[0] for q in reqs]
+                X = t.cat(ops, dim=1) if len(ops) > 1 else ops[0]
+                X = X.t().contiguous().t()
+                Y = t.zeros_like(X)
+                self.be.matvec(res.obj, X, Y, acc64, stream)
+                outs[(key, acc64)] = (reqs, Y, [o.shape[1] for o in ops])
+            self.batched_products += 1
+        # advance (same stream as the group's product)
+        for gk, (reqs, Y, widths) in outs.items():
+            stream = self.resident[gk[0]].stream
+            ctx = t.cuda.stream(stream) if stream is not None else _nullcontext()
+            with ctx:
+                c0 = 0
+                for q, w in zip(reqs, widths):
+                    self._advance(q, Y[:, c0:c0 + w])
+                    c0 += w
+        if self.be.device.type == "cuda":
+            t.cuda.synchronize()
+        self._retire()
+        self.ticks += 1
+        return len(outs)
+
+    def _advance(self, q, Y):
+        q.products += 1
+        if q._phase == "outer":
+            R = q.b - Y
+            nb = self.t.linalg.vector_norm(q.b, dim=0)
+            q._resid = (self.t.linalg.vector_norm(R, dim=0) / self.t.where(nb > 0, nb, self.t.ones_like(nb)))
+            q._outer_R = R
+            return
+        s = q._solver
+        s.advance(Y)
+        q.iterations += 1
+
+    def _retire(self):
+        t = self.t
+        now = None
+        keep = []
+        for q in self.active:
+            finished = False
+            if q._phase == "outer":
+                rel = float(q._resid.max())
+                if not math.isfinite(rel):
+                    q.status, q.error, finished = "failed", "non-finite residual", True
+                elif rel <= q.rtol:
+                    q.status, finished = "done", True
+                    q.rel_residual = rel
+                elif q.iterations >= q.maxit:
+                    q.status, finished = "not_converged", True
+                    q.rel_residual = rel
+                else:
+                    q._phase = "inner"
+                    tol = max(q.inner_rtol, 0.5 * q.rtol / rel)
+                    q._solver = self._new_solver(q, q._outer_R, tol)
+            else:
+                s = q._solver
+                if isinstance(s, _GMRES):
+                    if s.fresh():                   # true residual of the current iterate
+                        converged = float(s.relres().max()) <= s.tol
+                        exhausted = s.it >= s.maxit
+                    else:
+                        s.step_done()
+                        converged = exhausted = False
+                else:
+                    converged = float(s.relres().max()) <= s.tol
+                    exhausted = s.it >= s.maxit
+                relmax = float(s.relres().max())
+                if not math.isfinite(relmax):
+                    q.status, q.error, finished = "failed", "non-finite residual", True
+                elif converged:
+                    if self._refine(q):
+                        q._z = q._z + s.solution()
+                        q._phase = "outer"
+                    else:
+                        q._z = s.solution()
+                        q.status, finished = "done", True
+                        q.rel_residual = relmax
+                elif exhausted or q.iterations >= q.maxit:
+                    if isinstance(s, _GMRES) and s.phase == "arnoldi":
+                        s.close_cycle()
+                    q._z = (q._z + s.solution()) if self._refine(q) else s.solution()
+                    q.status, finished = "not_converged", True
+                    q.rel_residual = relmax
+            if finished:
+                now = self.clock() if now is None else now
+                q.finish = now
+                q.result = q._z
+                q._solver = None
+                self.resident[q.key].active -= 1
+                self.finished.append(q)
+            else:
+                keep.append(q)
+        self.active = keep
+
+    def run(self, until_idle=True, max_ticks=10 ** 9):
+        while (self.queue or self.active) and self.ticks < max_ticks:
+            if not self.active and self.queue and min(q.arrival for q in self.queue) > self.clock():
+                time.sleep(min(1e-3, max(0.0, min(q.arrival for q in self.queue) - self.clock())))
+                continue
+            n = self.tick()
+            if n == 0 and not self.active and not self.queue:
+                break
+            if n == 0 and self.queue and not self.active:
+                # nothing admissible right now (memory or arrivals): do not spin on a stuck queue
+                if all(q.arrival <= self.clock() for q in self.queue):
+                    for q in self.queue:
+                        q.status, q.error, q.finish = "failed", "does not fit the memory budget", self.clock()
+                        self.finished.append(q)
+                    self.queue = []
+
+    def stats(self) -> dict:
+        done = [q for q in self.finished if q.status == "done"]
+        lat = np.array([q.latency for q in done]) if done else np.zeros(0)
+        span = (max(q.finish for q in self.finished) - min(q.arrival for q in self.finished)) if self.finished else 0.0
+        return {
+            "requests": len(self.finished), "done": len(done),
+            "failed": sum(q.status == "failed" for q in self.finished),
+            "not_converged": sum(q.status == "not_converged" for q in self.finished),
+            "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_s": float(lat.mean()) if lat.size else None,
+            "throughput_req_s": len(done) / span if span > 0 else None,
+            "rhs_solved": int(sum(q.b.shape[1] for q in done)),
+            "ticks": self.ticks, "batched_products": self.batched_products,
+        }
+
+
+class _nullcontext:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
