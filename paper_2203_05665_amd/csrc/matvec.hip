@@ -707,6 +707,10 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
   if (ldx < H.S.n || ldy < H.S.n) throw Error(H2_EINVAL, "leading dimension smaller than n");
   const bool acc64 = (flags & H2_ACC_F64) != 0;
   if (cx) {
+    if (nrhs >= 2 && !acc64 && matvec_multi_supported(H)) {
+      matvec_multi(H, nrhs, dtype, x, ldx, y, ldy, alpha, st);
+      return;
+    }
     const size_t es = dtype == H2_C128 ? 16 : 8;
     for (int j = 0; j < nrhs; ++j) {
       const void* xj = static_cast<const char*>(x) + static_cast<size_t>(j) * ldx * es;

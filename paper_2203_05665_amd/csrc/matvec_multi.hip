@@ -308,6 +308,170 @@ __global__ __launch_bounds__(256) void mnear_backward(int nleaves, const int32_t
       }
 }
 
+// ---------------------------------------------------------------- complex (Helmholtz) many-RHS path
+// 16 complex right-hand sides per pass are held as 32 real columns [re | im];
+// the real V and E act on them with the real kernels above.  Complex S and
+// near-field entries (interleaved re, im) multiply as C1 = Re(A) [Xr | Xi] and
+// C2 = Im(A) [Xr | Xi]; then Yr = C1[:, :16] - C2[:, 16:], Yi = C1[:, 16:] +
+// C2[:, :16], one lane exchange (xor 16) per output element.
+template <typename XT>
+__global__ void mpermute_in_c(int64_t n, int rcur, const int32_t* __restrict__ perm, const XT* __restrict__ x,
+                              int64_t ldx, float* __restrict__ xc) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n * 32) return;
+  const int64_t p = e / 32;
+  const int j = static_cast<int>(e % 32), jc = j % 16, part = j / 16;
+  xc[e] = jc < rcur ? static_cast<float>(x[2 * (static_cast<int64_t>(jc) * ldx + perm[p]) + part]) : 0.f;
+}
+
+template <typename XT>
+__global__ void mpermute_out_c(int64_t n, int rcur, const int32_t* __restrict__ perm, const float* __restrict__ yc,
+                               XT* __restrict__ y, int64_t ldy, double alpha) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n * rcur * 2) return;
+  const int64_t p = e / (2 * rcur);
+  const int rem = static_cast<int>(e % (2 * rcur)), jc = rem / 2, part = rem % 2;
+  XT* dst = y + 2 * (static_cast<int64_t>(jc) * ldy + perm[p]) + part;
+  *dst = static_cast<XT>(static_cast<double>(*dst) + alpha * static_cast<double>(yc[p * 32 + 16 * part + jc]));
+}
+
+__device__ inline float combine_c(float c1, float c2) {
+  const float other = __shfl_xor(c2, 16);
+  return (threadIdx.x % 32) < 16 ? c1 - other : c1 + other;
+}
+
+// C1[ti] += Re(A) B, C2[ti] += Im(A) B; A complex row-major 64 x 64 (interleaved),
+// Bt right-hand-side-major 32 columns; kk mapping as in mma64_rowA
+__device__ inline void mma64_rowA_c(const float* __restrict__ A, const float* __restrict__ Bt, f32x16 (&C1)[2],
+                                    f32x16 (&C2)[2]) {
+  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    float ar[2][4][4], ai[2][4][4];
+    f4v b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 8 * (4 * half + q) + 4 * h;
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        const f4v u = ld4c(A + (32 * ti + r) * 128 + 2 * kk), w = ld4c(A + (32 * ti + r) * 128 + 2 * kk + 4);
+        ar[ti][q][0] = u.x; ai[ti][q][0] = u.y; ar[ti][q][1] = u.z; ai[ti][q][1] = u.w;
+        ar[ti][q][2] = w.x; ai[ti][q][2] = w.y; ar[ti][q][3] = w.z; ai[ti][q][3] = w.w;
+      }
+      b[q] = ld4c(Bt + r * 64 + kk);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti) {
+          C1[ti] = mfma(ar[ti][q][e], b[q][e], C1[ti]);
+          C2[ti] = mfma(ai[ti][q][e], b[q][e], C2[ti]);
+        }
+  }
+}
+
+// C1 += Re(A) B, C2 += Im(A) B; A complex column-major (element (i, kk) at
+// A[2 (kk lda + i)] and +1), B position-major 32 columns; clamped loads as in mma_colA
+__device__ inline void mma_colA_c(const float* __restrict__ A, int lda, int mrows, const float* __restrict__ B,
+                                  int kcount, f32x16 (&C1)[2], f32x16 (&C2)[2]) {
+  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+  const bool row0 = r < mrows, row1 = r + 32 < mrows;
+  const float* a0 = A + 2 * min(r, mrows - 1);
+  const float* a1 = A + 2 * min(r + 32, mrows - 1);
+  const float* b = B + r;
+  const int steps = min(32, kcount);
+#pragma unroll 2
+  for (int k0 = 0; k0 < steps; k0 += 4) {
+    float ar[2][4], ai[2][4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + u + 32 * h;
+      const bool ok = kk < kcount;
+      const int kc = min(kk, kcount - 1);
+      const float2 x0 = *reinterpret_cast<const float2*>(a0 + 2 * kc * lda);
+      const float2 x1 = *reinterpret_cast<const float2*>(a1 + 2 * kc * lda);
+      ar[0][u] = (ok && row0) ? x0.x : 0.f;
+      ai[0][u] = (ok && row0) ? x0.y : 0.f;
+      ar[1][u] = (ok && row1) ? x1.x : 0.f;
+      ai[1][u] = (ok && row1) ? x1.y : 0.f;
+      const float y = b[kc * 32];
+      bv[u] = ok ? y : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        C1[ti] = mfma(ar[ti][u], bv[u], C1[ti]);
+        C2[ti] = mfma(ai[ti][u], bv[u], C2[ti]);
+      }
+  }
+}
+
+__global__ __launch_bounds__(256) void mcoupling_c(int nc, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col, const float* __restrict__ S,
+                                                   const float* __restrict__ xhat, float* __restrict__ yhat) {
+  const int64_t tau = xcd_item(nc);
+  if (tau >= nc) return;
+  f32x16 C1[2][1], C2[2][1];
+  zero(C1);
+  zero(C2);
+  f32x16 c1[2] = {C1[0][0], C1[1][0]}, c2[2] = {C2[0][0], C2[1][0]};
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau]; b < b1; ++b)
+    mma64_rowA_c(S + b * 8192, xhat + static_cast<int64_t>(col[b]) * 32 * 64, c1, c2);
+  const int l = threadIdx.x % 64;
+  float* out = yhat + tau * 32 * 64;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) out[(l % 32) * 64 + 32 * ti + acc_row(v, l)] = combine_c(c1[ti][v], c2[ti][v]);
+}
+
+__global__ __launch_bounds__(256) void mnear_backward_c(int nleaves, const int32_t* __restrict__ leaves,
+                                                        const int32_t* __restrict__ cbegin,
+                                                        const int32_t* __restrict__ cend,
+                                                        const int64_t* __restrict__ near_ptr,
+                                                        const int32_t* __restrict__ near_col,
+                                                        const int64_t* __restrict__ panel_off,
+                                                        const float* __restrict__ N, const float* __restrict__ Vb,
+                                                        const float* __restrict__ xc, const float* __restrict__ yhat,
+                                                        float* __restrict__ yc) {
+  const int64_t it = xcd_item(nleaves);
+  if (it >= nleaves) return;
+  const int l = threadIdx.x % 64;
+  const int32_t tau = leaves[it];
+  const int64_t b0 = cbegin[tau];
+  const int r = cend[tau] - cbegin[tau];
+  const float* P = N + 2 * panel_off[it];
+  f32x16 c1[2], c2[2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) c1[ti][v] = c2[ti][v] = 0.f;
+  int64_t colbase = 0;
+  for (int64_t bb = near_ptr[it]; bb < near_ptr[it + 1]; ++bb) {
+    const int32_t s = near_col[bb];
+    const int64_t s0 = cbegin[s];
+    const int wdt = cend[s] - cbegin[s];
+    mma_colA_c(P + 2 * colbase * r, r, r, xc + s0 * 32, wdt, c1, c2);
+    colbase += wdt;
+  }
+  // leaf backward: real V times [y^r | y^i] adds to the real-part accumulator only
+  f32x16 accv[2][1] = {{c1[0]}, {c1[1]}};
+  mma_colA_Bt<1>(Vb + b0 * 64, r, r, yhat + static_cast<int64_t>(tau) * 32 * 64, accv);
+  float* out = yc + b0 * 32 + l % 32;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 32 * ti + acc_row(v, l);
+      const float val = combine_c(accv[ti][0][v], c2[ti][v]);   // every lane takes part in the exchange
+      if (i < r) out[i * 32] = val;
+    }
+}
+
 inline unsigned nblk(int64_t work, int per) {
   const int64_t g = (work + per - 1) / per;
   if (g > 0x7fffffff) throw Error(H2_EINVAL, "launch too large");
@@ -380,10 +544,75 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
   }
 }
 
+template <typename XT>
+void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t ldy, double alpha,
+                hipStream_t st) {
+  const Structure& S = H.S;
+  const int64_t n = S.n;
+  const int nc = S.nclusters;
+  const int nl = static_cast<int>(S.leaves.size());
+  float* xc = H.mxc.as<float>();
+  float* yc = H.myc.as<float>();
+  float* xh = H.mxhat.as<float>();
+  float* yh = H.myhat.as<float>();
+  auto grid8 = [&](int64_t items) {
+    const unsigned g = nblk((items + 3) / 4 * 4, 4);
+    return (g + 7) / 8 * 8;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+  if (H.prof) {
+    e0 = prof_event(H);
+    H2_HIP(hipEventRecord(e0, st));
+  }
+  mpermute_in_c<XT><<<nblk(n * 32, 256), 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), x, ldx, xc);
+  mleaf_forward<1><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                              H.cend.as<int32_t>(), H.Vf.as<float>(), xc, xh);
+  for (int lv = S.depth - 1; lv >= 0; --lv) {
+    const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
+    if (cnt == 0) continue;
+    mtransfer_up<1><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv], H.child0.as<int32_t>(),
+                                                H.child1.as<int32_t>(), H.ET.as<float>(), xh);
+  }
+  if (H.prof) {
+    e1 = prof_event(H);
+    H2_HIP(hipEventRecord(e1, st));
+  }
+  mcoupling_c<<<grid8(nc), 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<float>(),
+                                         xh, yh);
+  if (H.prof) {
+    e2 = prof_event(H);
+    H2_HIP(hipEventRecord(e2, st));
+  }
+  for (int lv = 0; lv < S.depth; ++lv) {
+    const int first = S.level_ptr[lv + 1], cnt = S.level_ptr[lv + 2] - S.level_ptr[lv + 1];
+    if (cnt == 0) continue;
+    mtransfer_down<1><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
+  }
+  if (H.prof) {
+    e3 = prof_event(H);
+    H2_HIP(hipEventRecord(e3, st));
+  }
+  mnear_backward_c<<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                              H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                              H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<float>(),
+                                              H.Vb.as<float>(), xc, yh, yc);
+  mpermute_out_c<XT><<<nblk(n * rcur * 2, 256), 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha);
+  H2_HIP(hipGetLastError());
+  if (H.prof) {
+    e4 = prof_event(H);
+    H2_HIP(hipEventRecord(e4, st));
+    prof_record(H, H2_PH_FORWARD, e0, e1);
+    prof_record(H, H2_PH_COUPLING, e1, e2);
+    prof_record(H, H2_PH_DOWN, e2, e3);
+    prof_record(H, H2_PH_NEAR, e3, e4);
+    prof_record(H, H2_PH_TOTAL, e0, e4);
+  }
+}
+
 }  // namespace
 
 bool matvec_multi_supported(const h2_handle_s& H) {
-  if (H.host_only || H.is_complex || H.P.storage != H2_F32 || H.S.k != 64) return false;
+  if (H.host_only || H.P.storage != H2_F32 || H.S.k != 64) return false;
   for (int32_t c : H.S.leaves)
     if (H.S.cend[c] - H.S.cbegin[c] > 64) return false;  // one MFMA K-chunk per leaf
   return true;
@@ -391,7 +620,8 @@ bool matvec_multi_supported(const h2_handle_s& H) {
 
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
                   double alpha, hipStream_t st) {
-  const int rp = nrhs <= 32 ? 32 : 64;
+  const bool cx = dtype == H2_C128 || dtype == H2_C64;
+  const int rp = cx ? 32 : (nrhs <= 32 ? 32 : 64);
   const Structure& S = H.S;
   const size_t need_v = static_cast<size_t>(S.n) * rp * 4, need_h = static_cast<size_t>(S.nclusters) * 64 * rp * 4;
   if (H.mxc.bytes < need_v || H.mxhat.bytes < need_h) {
@@ -401,6 +631,19 @@ void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ld
     H.myc.alloc(need_v);
     H.mxhat.alloc(need_h);
     H.myhat.alloc(need_h);
+  }
+  if (cx) {  // 16 complex columns per pass
+    const size_t ces = dtype == H2_C128 ? 16 : 8;
+    for (int j0 = 0; j0 < nrhs; j0 += 16) {
+      const int rcur = std::min(16, nrhs - j0);
+      const void* xj = static_cast<const char*>(x) + static_cast<size_t>(j0) * ldx * ces;
+      void* yj = static_cast<char*>(y) + static_cast<size_t>(j0) * ldy * ces;
+      if (dtype == H2_C128)
+        run_pass_c<double>(H, rcur, static_cast<const double*>(xj), ldx, static_cast<double*>(yj), ldy, alpha, st);
+      else
+        run_pass_c<float>(H, rcur, static_cast<const float*>(xj), ldx, static_cast<float*>(yj), ldy, alpha, st);
+    }
+    return;
   }
   const size_t es = dtype == H2_R64 ? 8 : 4;
   for (int j0 = 0; j0 < nrhs; j0 += rp) {
