@@ -220,12 +220,85 @@ def bench_multi(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Poisson stream of solve requests served with continuous batching."""
+    import numpy as np
+    import torch
+
+    import h2_inputs as I
+    from paper_2203_05665_amd.serve import GPUBackend, H2Server
+
+    meshes = {"sphere%d" % r: I.icosphere(r) for r in (4, 5, 6, 7)}
+    meshes.update({"cube%d" % N: I.cube_surface(N) for N in (32, 64, 128)})
+    kernels = [("laplace", 0.0), ("helmholtz", 2.0), ("helmholtz", 4.0)]
+    S = H2Server(GPUBackend(order=4, leaf=64, eta=0.5, storage="f32"), mem_budget=args.serve_budget_gb * 1e9,
+                 max_active=args.serve_slots)
+    for name, (V, T) in meshes.items():
+        S.register_mesh(name, V, T)
+    t0 = time.perf_counter()
+    for name in meshes:                       # structures are built once and stay resident
+        for kern, kap in kernels:
+            S._make_resident((name, kern, float(kap)), 0)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log("serve: %d structures resident, %.1f GB, built in %.1f s" % (len(S.resident), S.used_bytes() / 1e9, build_s))
+    rng = np.random.default_rng(5)
+    names = sorted(meshes)
+    gaps = rng.exponential(1.0 / args.serve_rate, args.serve_requests)
+    arrivals = np.cumsum(gaps)
+    reqs_spec = []
+    for i in range(args.serve_requests):
+        name = names[rng.integers(len(names))]
+        kern, kap = kernels[rng.integers(3)]
+        r = int(rng.integers(1, 17))
+        V, T = meshes[name]
+        P = V[T]
+        area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+        B = rng.standard_normal((T.shape[0], r))
+        if kern == "helmholtz":
+            B = B + 1j * rng.standard_normal((T.shape[0], r))
+        B[:, 0] = area
+        reqs_spec.append((name, kern, kap, B))
+    start = S.clock() + 0.05
+    for (name, kern, kap, B), a in zip(reqs_spec, arrivals):
+        S.submit(name, B, kernel=kern, kappa=kap, rtol=1e-8, arrival=start + a)
+    S.run(progress=lambda d: log("serve progress:", json.dumps(d)), progress_every=10.0,
+          deadline=start + args.serve_deadline_s)
+    torch.cuda.synchronize()
+    st = S.stats()
+    span = max(q.finish for q in S.finished) - start
+    out = {
+        "metric": "served solves/s", "value": st["done"] / span, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.serve_requests, "warmup": 0, "ms_per_step": 1e3 * span / max(1, st["done"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-refinement",
+        "data": "synthetic",
+        "config": {"workload": "serve_mix", "meshes": {k: int(v[1].shape[0]) for k, v in meshes.items()},
+                   "kernels": ["laplace", "helmholtz k=2", "helmholtz k=4"], "rhs": "U{1..16}",
+                   "arrival_rate_per_s": args.serve_rate, "rtol": 1e-8, "slots": args.serve_slots,
+                   "storage": "f32 (FP64 iterative refinement)"},
+        "serving": dict(st, build_s=build_s, span_s=span, resident_GB=S.used_bytes() / 1e9,
+                        iterations_mean=float(np.mean([q.iterations for q in S.finished])),
+                        iterations_by_kernel={k: float(np.mean([q.iterations for q in S.finished if q.kernel == k]))
+                                              for k in ("laplace", "helmholtz")},
+                        latency_p50_by_kernel={k: float(np.percentile([q.latency for q in S.finished
+                                                                       if q.kernel == k and q.status == "done"], 50))
+                                               for k in ("laplace", "helmholtz")}),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sphere1310k_m4_f32", choices=sorted(WORKLOADS) + sorted(MULTI))
+    ap.add_argument("--workload", default="sphere1310k_m4_f32",
+                    choices=sorted(WORKLOADS) + sorted(MULTI) + ["serve_mix"])
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-budget-gb", type=float, default=220.0)
+    ap.add_argument("--serve-deadline-s", type=float, default=150.0, help="cancel what is unfinished after this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison run")
     ap.add_argument("--copy-probe", action="store_true", help="also time a device copy of known size")
@@ -243,6 +316,8 @@ def main():
 
     if args.workload in MULTI:
         return bench_multi(args)
+    if args.workload == "serve_mix":
+        return bench_serve(args)
     kind, level, order, leaf, storage, seed = WORKLOADS[args.workload]
     V, T = I.mesh_for(kind, level)
     n = T.shape[0]

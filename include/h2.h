@@ -178,6 +178,23 @@ const char* h2_last_error(void);
 #define H2_X_N 9
 int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap);
 
+/* Batched Krylov vector kernels for many independent right-hand sides (the
+ * Gram-Schmidt and update steps of GMRES; Introduction: Krylov methods).
+ * dtype H2_R64 (double) or H2_C128 (interleaved complex double); DEVICE data:
+ *   Q: element k of basis vector i of right-hand side r at
+ *      Q[r * q_rhs_stride + i * q_vec_stride + k]   (strides in elements)
+ *   W: element k of right-hand side r at W[r * w_rhs_stride + k]
+ *   h: nrhs x nvec, row-major.
+ * h2_krylov_dots:   h[r][i] = sum_k conj(Q[r][i][k]) W[r][k]
+ * h2_krylov_update: W[r][k] += sign * sum_i h[r][i] Q[r][i][k]
+ * Asynchronous on `stream`; deterministic (fixed reduction order); no handle
+ * and no allocation. */
+int h2_krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t q_rhs_stride,
+                   int64_t q_vec_stride, const void* W, int64_t w_rhs_stride, void* h, void* stream);
+int h2_krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t q_rhs_stride,
+                     int64_t q_vec_stride, const void* h, double sign, void* W, int64_t w_rhs_stride,
+                     void* stream);
+
 /* Per-phase device timing of h2_matvec (HIP events on the call's stream).
  * h2_profile(h, 1) enables and clears; h2_profile(h, 0) disables.
  * h2_profile_read fills ms[H2_NPHASE] with summed milliseconds and

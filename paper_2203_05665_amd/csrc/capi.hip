@@ -306,6 +306,24 @@ int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap) {
   });
 }
 
+int h2_krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t q_rhs_stride,
+                   int64_t q_vec_stride, const void* W, int64_t w_rhs_stride, void* h, void* stream) {
+  return guarded([&]() -> int {
+    h2::krylov_dots(dtype, nrhs, nvec, n, Q, q_rhs_stride, q_vec_stride, W, w_rhs_stride, h,
+                    static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
+int h2_krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t q_rhs_stride,
+                     int64_t q_vec_stride, const void* h, double sign, void* W, int64_t w_rhs_stride, void* stream) {
+  return guarded([&]() -> int {
+    h2::krylov_update(dtype, nrhs, nvec, n, Q, q_rhs_stride, q_vec_stride, h, sign, W, w_rhs_stride,
+                      static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
 int h2_profile(h2_handle h, int enable) {
   return guarded([&]() -> int {
     if (!h) return fail(H2_EINVAL, "NULL handle");

@@ -96,6 +96,10 @@ void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ld
                   double alpha, hipStream_t s);
 int solve(h2_handle_s& H, const void* b, void* z, const h2_solve_params& p, h2_solve_info& info,
           hipStream_t s);
+void krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* W,
+                 int64_t wr, void* h, hipStream_t st);
+void krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* h,
+                   double sign, void* W, int64_t wr, hipStream_t st);
 hipEvent_t prof_event(h2_handle_s& H);
 void prof_record(h2_handle_s& H, int phase, hipEvent_t a, hipEvent_t b);
 }  // namespace h2

@@ -83,7 +83,12 @@ def lib():
         L.h2_export.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64]
         L.h2_profile.argtypes = [C.c_void_p, C.c_int]
         L.h2_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
-        for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read"):
+        L.h2_krylov_dots.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                     C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.h2_krylov_update.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                       C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]
+        for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
+                  "h2_krylov_dots", "h2_krylov_update"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -167,6 +172,38 @@ def h2_solve(h, b, z, method="cg", rtol=1e-8, maxit=1000, restart=50, refine=Fal
         _check(rc)
     return dict(iterations=info.iterations, outer=info.outer, rel_residual=info.rel_residual,
                 seconds=info.seconds, converged=rc == H2_OK)
+
+
+def _kdtype(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return H2_C128
+    if t.dtype == torch.float64:
+        return H2_R64
+    raise TypeError("Krylov kernels take float64 or complex128 tensors")
+
+
+def h2_krylov_dots(Q, W, nvec, stream=None):
+    """h[r, i] = sum_k conj(Q[r, i, k]) W[r, k] for i < nvec; Q (r, m, n), W (r, n), unit last stride."""
+    import torch
+    r, _, n = Q.shape
+    if Q.stride(2) != 1 or W.stride(1) != 1 or W.dtype != Q.dtype or W.shape != (r, n):
+        raise ValueError("bad Krylov operands")
+    h = torch.empty((r, nvec), dtype=Q.dtype, device=Q.device)
+    _check(lib().h2_krylov_dots(_kdtype(Q), r, nvec, n, Q.data_ptr(), Q.stride(0), Q.stride(1), W.data_ptr(),
+                                W.stride(0), h.data_ptr(), _stream(stream)))
+    return h
+
+
+def h2_krylov_update(Q, h, W, sign=1.0, stream=None):
+    """W[r, k] += sign * sum_i h[r, i] Q[r, i, k] for i < h.shape[1]."""
+    r, nvec = h.shape
+    n = W.shape[1]
+    if Q.stride(2) != 1 or W.stride(1) != 1 or not h.is_contiguous() or h.dtype != Q.dtype or W.dtype != Q.dtype:
+        raise ValueError("bad Krylov operands")
+    _check(lib().h2_krylov_update(_kdtype(Q), r, nvec, n, Q.data_ptr(), Q.stride(0), Q.stride(1), h.data_ptr(),
+                                  float(sign), W.data_ptr(), W.stride(0), _stream(stream)))
+    return W
 
 
 def h2_info(h) -> dict:

@@ -80,12 +80,38 @@ class GPUBackend:
     def refine(self):
         return self.storage != "f64"
 
+    # batched Gram-Schmidt kernels of the library (current stream)
+    def krylov_dots(self, Q, W, nvec):
+        return self.h2.h2_krylov_dots(Q, W, nvec)
+
+    def krylov_update(self, Q, h, W, sign):
+        self.h2.h2_krylov_update(Q, h.contiguous(), W, sign)
+
+
+class _TensorKrylov:
+    """Plain tensor versions of the batched Gram-Schmidt steps (for backends
+    without native kernels, e.g. the CPU test backend)."""
+
+    @staticmethod
+    def krylov_dots(Q, W, nvec):
+        Qj = Q[:, :nvec]
+        return ((Qj.conj() if Qj.is_complex() else Qj) * W[:, None, :]).sum(-1)
+
+    @staticmethod
+    def krylov_update(Q, h, W, sign):
+        W += sign * (h[:, :, None] * Q[:, : h.shape[1]]).sum(1)
+
 
 # ---------------------------------------------------------------------------- Krylov state machines
 
 
+# All Krylov vectors are held right-hand-side-major, shape (r, n): row c is
+# column c of the n x r block, so X.t() is the Fortran-ordered n x r block the
+# product takes, with no copy.
+
+
 class _CG:
-    """Conjugate gradients for all columns of B at once (independent columns)."""
+    """Conjugate gradients for all right-hand sides at once (independent columns)."""
 
     def __init__(self, torch, B, tol, maxit):
         self.t = torch
@@ -93,22 +119,23 @@ class _CG:
         self.X = torch.zeros_like(B)
         self.R = B.clone()
         self.P = B.clone()
-        self.rr = (B * B).sum(0)
-        self.nb = self.t.sqrt(self.rr)
+        self.rr = (B * B).sum(1)
+        self.nb = torch.sqrt(self.rr)
         self.tol, self.maxit, self.it = tol, maxit, 0
-        self.done = bool((self.nb == 0).all())
 
     def operand(self):
         return self.P
 
     def advance(self, Q):
         t = self.t
-        pq = (self.P * Q).sum(0)
-        alpha = t.where(pq > 0, self.rr / t.where(pq > 0, pq, t.ones_like(pq)), t.zeros_like(pq))
+        pq = (self.P * Q).sum(1)
+        ok = pq > 0
+        alpha = t.where(ok, self.rr / t.where(ok, pq, t.ones_like(pq)), t.zeros_like(pq))[:, None]
         self.X += alpha * self.P
         self.R -= alpha * Q
-        rr2 = (self.R * self.R).sum(0)
-        beta = t.where(self.rr > 0, rr2 / t.where(self.rr > 0, self.rr, t.ones_like(self.rr)), t.zeros_like(rr2))
+        rr2 = (self.R * self.R).sum(1)
+        okr = self.rr > 0
+        beta = t.where(okr, rr2 / t.where(okr, self.rr, t.ones_like(self.rr)), t.zeros_like(rr2))[:, None]
         self.P = self.R + beta * self.P
         self.rr = rr2
         self.it += 1
@@ -122,49 +149,44 @@ class _CG:
 
 
 class _GMRES:
-    """Restarted GMRES for all columns of B at once (independent Arnoldi
-    processes advanced in lockstep; classical Gram-Schmidt twice; complex
-    Givens rotations), FP64 / complex128.
+    """Restarted GMRES for all right-hand sides at once (independent Arnoldi
+    processes advanced in lockstep; classical Gram-Schmidt twice as batched
+    matrix-vector products; complex Givens rotations), FP64 / complex128.
 
     phase "arnoldi": the next product is A q_j;  phase "residual": the next
-    product is A X (true residual at the end of a restart cycle);  phase
-    "converged": every column meets the tolerance."""
+    product is A X (true residual at the end of a restart cycle)."""
 
-    def __init__(self, torch, B, tol, maxit, restart):
+    def __init__(self, torch, B, tol, maxit, restart, ops):
         self.t = torch
+        self.ops = ops
         self.B = B
         self.m = restart
         self.tol, self.maxit, self.it = tol, maxit, 0
         self.X = torch.zeros_like(B)
-        n, r = B.shape
-        self.nb = torch.linalg.vector_norm(B, dim=0)
-        self.Q = torch.zeros((self.m + 1, n, r), dtype=B.dtype, device=B.device)
+        r, n = B.shape
+        self.nb = torch.linalg.vector_norm(B, dim=1)
+        self.Q = torch.zeros((r, self.m + 1, n), dtype=B.dtype, device=B.device)
         cdt = torch.complex128
-        self.H = torch.zeros((self.m + 1, self.m, r), dtype=cdt, device=B.device)
+        self.H = torch.zeros((r, self.m + 1, self.m), dtype=cdt, device=B.device)
         self.cs = torch.zeros((self.m, r), dtype=cdt, device=B.device)
         self.sn = torch.zeros((self.m, r), dtype=cdt, device=B.device)
         self.g = torch.zeros((self.m + 1, r), dtype=cdt, device=B.device)
         self.j = 0
-        self._rel = torch.ones(r, dtype=torch.float64, device=B.device)
         self._start(B)                       # X = 0: the residual is B itself
 
     def _start(self, R):
         t = self.t
-        beta = t.linalg.vector_norm(R, dim=0)
+        beta = t.linalg.vector_norm(R, dim=1)
         self._rel = beta / t.where(self.nb > 0, self.nb, t.ones_like(self.nb))
-        self.Q.zero_()
         self.H.zero_()
         self.g.zero_()
-        self.Q[0] = R / t.where(beta > 0, beta, t.ones_like(beta)).to(R.dtype)
+        self.Q[:, 0, :] = R / t.where(beta > 0, beta, t.ones_like(beta)).to(R.dtype)[:, None]
         self.g[0] = beta.to(self.g.dtype)
         self.j = 0
         self.phase = "arnoldi"
 
     def operand(self):
-        return self.X if self.phase == "residual" else self.Q[self.j]
-
-    def _cdot(self, a, b):  # column-wise conj(a).b
-        return (a.conj() * b).sum(0) if a.is_complex() else (a * b).sum(0)
+        return self.X if self.phase == "residual" else self.Q[:, self.j, :]
 
     def advance(self, Y):
         t = self.t
@@ -173,15 +195,16 @@ class _GMRES:
             return
         j = self.j
         W = Y.clone()
-        hcol = t.zeros((self.m + 1, W.shape[1]), dtype=self.H.dtype, device=W.device)
-        Qj = self.Q[: j + 1]
-        for _ in range(2):                                                  # classical Gram-Schmidt, twice
-            h = t.einsum("inr,nr->ir", Qj.conj() if W.is_complex() else Qj, W)  # (j+1, r)
-            W = W - t.einsum("ir,inr->nr", h, Qj)
-            hcol[: j + 1] += h.to(hcol.dtype)
-        hn = t.linalg.vector_norm(W, dim=0)
+        hsum = t.zeros((W.shape[0], j + 1), dtype=self.H.dtype, device=W.device)
+        for _ in range(2):                                           # classical Gram-Schmidt, twice
+            h = self.ops.krylov_dots(self.Q, W, j + 1)               # (r, j+1) = <q_i, w>
+            self.ops.krylov_update(self.Q, h, W, -1.0)
+            hsum += h.to(hsum.dtype)
+        hn = t.linalg.vector_norm(W, dim=1)
+        hcol = t.zeros((self.m + 1, W.shape[0]), dtype=self.H.dtype, device=W.device)
+        hcol[: j + 1] = hsum.t()
         hcol[j + 1] = hn.to(hcol.dtype)
-        self.Q[j + 1] = W / t.where(hn > 0, hn, t.ones_like(hn)).to(W.dtype)
+        self.Q[:, j + 1, :] = W / t.where(hn > 0, hn, t.ones_like(hn)).to(W.dtype)[:, None]
         for i in range(j):
             tmp = self.cs[i] * hcol[i] + self.sn[i] * hcol[i + 1]
             hcol[i + 1] = -self.sn[i].conj() * hcol[i] + self.cs[i] * hcol[i + 1]
@@ -198,7 +221,7 @@ class _GMRES:
         hcol[j + 1] = 0
         self.g[j + 1] = -self.sn[j].conj() * self.g[j]
         self.g[j] = self.cs[j] * self.g[j]
-        self.H[:, j] = hcol
+        self.H[:, :, j] = hcol.t()
         self.it += 1
         self.j += 1
         self._rel = self.g[self.j].abs() / t.where(self.nb > 0, self.nb, t.ones_like(self.nb))
@@ -208,12 +231,13 @@ class _GMRES:
         t = self.t
         k = self.j
         if k > 0:
-            Hk = self.H[:k, :k].permute(2, 0, 1)                      # (r, k, k)
-            gk = self.g[:k].permute(1, 0).unsqueeze(-1)               # (r, k, 1)
+            Hk = self.H[:, :k, :k]                                    # (r, k, k)
+            gk = self.g[:k].t().unsqueeze(-1)                         # (r, k, 1)
             diag = t.diagonal(Hk, dim1=1, dim2=2)
             Hk = Hk + t.diag_embed(t.where(diag == 0, t.ones_like(diag), t.zeros_like(diag)))
-            y = t.linalg.solve_triangular(Hk, gk, upper=True).squeeze(-1).permute(1, 0)   # (k, r)
-            self.X += t.einsum("kr,knr->nr", y if self.X.is_complex() else y.real, self.Q[:k])
+            y = t.linalg.solve_triangular(Hk, gk, upper=True)         # (r, k, 1)
+            yq = y.squeeze(-1) if self.X.is_complex() else y.squeeze(-1).real
+            self.ops.krylov_update(self.Q, yq.contiguous(), self.X, 1.0)
         self.phase = "residual"
         self.j = 0
 
@@ -313,16 +337,17 @@ class H2Server:
         if b.dim() == 1:
             b = b[:, None]
         cx = kernel == "helmholtz"
-        b = b.to(device=self.be.device, dtype=t.complex128 if cx else t.float64)
+        # held right-hand-side-major (r, n); results are returned as n x r views
+        b = b.to(device=self.be.device, dtype=t.complex128 if cx else t.float64).t().contiguous()
         req = Request(self._next, mesh, kernel, float(kappa), b, rtol=rtol,
                       arrival=self.clock() if arrival is None else arrival, **kw)
         self._next += 1
         if mesh not in self.meshes:
             req.status, req.error = "failed", "unknown mesh %r" % mesh
             self.finished.append(req)
-        elif b.shape[0] != self.meshes[mesh][1].shape[0]:
+        elif b.shape[1] != self.meshes[mesh][1].shape[0]:
             req.status, req.error = "failed", "right-hand side has %d rows, mesh has %d triangles" % (
-                b.shape[0], self.meshes[mesh][1].shape[0])
+                b.shape[1], self.meshes[mesh][1].shape[0])
             self.finished.append(req)
         elif not bool(t.isfinite(t.view_as_real(b) if cx else b).all()):
             req.status, req.error = "failed", "right-hand side is not finite"
@@ -336,7 +361,7 @@ class H2Server:
         return sum(r.nbytes for r in self.resident.values()) + sum(self._req_bytes(q) for q in self.active)
 
     def _req_bytes(self, q: Request) -> int:
-        n, r = q.b.shape
+        r, n = q.b.shape
         es = q.b.element_size()
         nvec = (q.restart + 6) if q.kernel == "helmholtz" else 8
         return int(n * r * es * nvec)
@@ -403,7 +428,8 @@ class H2Server:
     def _new_solver(self, q, rhs, tol):
         left = max(1, q.maxit - q.iterations)
         if q.kernel == "helmholtz":
-            return _GMRES(self.t, rhs, tol, left, q.restart)
+            ops = self.be if hasattr(self.be, "krylov_dots") else _TensorKrylov
+            return _GMRES(self.t, rhs, tol, left, q.restart, ops)
         return _CG(self.t, rhs, tol, left)
 
     def _operand(self, q) -> Tuple[object, bool]:
@@ -434,12 +460,11 @@ class H2Server:
             with ctx:
                 if stream is not None:       # right-hand sides were made on the submitting stream
                     stream.wait_stream(t.cuda.default_stream(stream.device))
-                ops = [self._operand(q)[0] for q in reqs]
-                X = t.cat(ops, dim=1) if len(ops) > 1 else ops[0]
-                X = X.t().contiguous().t()
-                Y = t.zeros_like(X)
-                self.be.matvec(res.obj, X, Y, acc64, stream)
-                outs[(key, acc64)] = (reqs, Y, [o.shape[1] for o in ops])
+                ops = [self._operand(q)[0] for q in reqs]           # (r_i, n) each
+                Xr = t.cat(ops, dim=0) if len(ops) > 1 else ops[0].contiguous()
+                Yr = t.zeros_like(Xr)
+                self.be.matvec(res.obj, Xr.t(), Yr.t(), acc64, stream)  # n x R Fortran views
+                outs[(key, acc64)] = (reqs, Yr, [o.shape[0] for o in ops])
             self.batched_products += 1
         # advance (same stream as the group's product)
         for gk, (reqs, Y, widths) in outs.items():
@@ -448,7 +473,7 @@ class H2Server:
             with ctx:
                 c0 = 0
                 for q, w in zip(reqs, widths):
-                    self._advance(q, Y[:, c0:c0 + w])
+                    self._advance(q, Y[c0:c0 + w])
                     c0 += w
         if self.be.device.type == "cuda":
             t.cuda.synchronize()
@@ -460,8 +485,8 @@ class H2Server:
         q.products += 1
         if q._phase == "outer":
             R = q.b - Y
-            nb = self.t.linalg.vector_norm(q.b, dim=0)
-            q._resid = (self.t.linalg.vector_norm(R, dim=0) / self.t.where(nb > 0, nb, self.t.ones_like(nb)))
+            nb = self.t.linalg.vector_norm(q.b, dim=1)
+            q._resid = (self.t.linalg.vector_norm(R, dim=1) / self.t.where(nb > 0, nb, self.t.ones_like(nb)))
             q._outer_R = R
             return
         s = q._solver
@@ -520,7 +545,7 @@ class H2Server:
             if finished:
                 now = self.clock() if now is None else now
                 q.finish = now
-                q.result = q._z
+                q.result = q._z.t()                 # n x r
                 q._solver = None
                 self.resident[q.key].active -= 1
                 self.finished.append(q)
@@ -528,8 +553,25 @@ class H2Server:
                 keep.append(q)
         self.active = keep
 
-    def run(self, until_idle=True, max_ticks=10 ** 9):
+    def run(self, until_idle=True, max_ticks=10 ** 9, progress: Optional[Callable[[dict], None]] = None,
+            progress_every: float = 5.0, deadline: Optional[float] = None):
+        """Serve until the queue and the slots are empty.  `progress` is called with
+        stats() at most every `progress_every` seconds; past `deadline` (clock
+        value) unfinished requests are cancelled (status "cancelled")."""
+        last = self.clock()
         while (self.queue or self.active) and self.ticks < max_ticks:
+            if deadline is not None and self.clock() > deadline:
+                for q in self.queue + self.active:
+                    q.status, q.error, q.finish = "cancelled", "deadline", self.clock()
+                    if q in self.active:
+                        self.resident[q.key].active -= 1
+                    self.finished.append(q)
+                self.queue, self.active = [], []
+                break
+            if progress is not None and self.clock() - last >= progress_every:
+                last = self.clock()
+                progress(dict(self.stats(), active=len(self.active), queued=len(self.queue),
+                              active_iterations=[q.iterations for q in self.active][:8]))
             if not self.active and self.queue and min(q.arrival for q in self.queue) > self.clock():
                 time.sleep(min(1e-3, max(0.0, min(q.arrival for q in self.queue) - self.clock())))
                 continue
@@ -551,12 +593,13 @@ class H2Server:
         return {
             "requests": len(self.finished), "done": len(done),
             "failed": sum(q.status == "failed" for q in self.finished),
+            "cancelled": sum(q.status == "cancelled" for q in self.finished),
             "not_converged": sum(q.status == "not_converged" for q in self.finished),
             "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_s": float(lat.mean()) if lat.size else None,
             "throughput_req_s": len(done) / span if span > 0 else None,
-            "rhs_solved": int(sum(q.b.shape[1] for q in done)),
+            "rhs_solved": int(sum(q.b.shape[0] for q in done)),
             "ticks": self.ticks, "batched_products": self.batched_products,
         }
 

@@ -119,7 +119,7 @@ def test_refinement_reaches_tolerance_of_rounded_operator():
     for req, A in ((q, dense(be, S, "sphere2")), (qc, dense(be, S, "sphere2", "helmholtz", 4.0))):
         assert req.status == "done"
         z = req.result.numpy()[:, 0]
-        rhs = req.b.numpy()[:, 0]
+        rhs = req.b.numpy()[0]          # requests hold right-hand sides as rows
         assert np.linalg.norm(A @ z - rhs) <= 1.01e-10 * np.linalg.norm(rhs)
 
 
