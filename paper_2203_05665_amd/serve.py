@@ -26,6 +26,7 @@ driven by a CPU backend in tests.
 from __future__ import annotations
 
 import math
+from collections import Counter
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Tuple
@@ -375,16 +376,18 @@ class H2Server:
 
     def _make_resident(self, key, extra) -> Optional[_Resident]:
         """The resident structure for `key`, building it if the budget allows after
-        evicting idle structures (least recently used first); None = wait."""
-        if key in self.resident:
-            return self.resident[key]
-        nbytes = self._footprint(key)
+        evicting idle structures (least recently used first) until the structure
+        and `extra` bytes of request vectors fit; None = wait."""
+        have = self.resident.get(key)
+        nbytes = 0 if have is not None else self._footprint(key)
         while self.used_bytes() + nbytes + extra > self.budget:
-            idle = [(r.last_used, k) for k, r in self.resident.items() if r.active == 0]
+            idle = [(r.last_used, k) for k, r in self.resident.items() if r.active == 0 and k != key]
             if not idle:
                 return None
             _, victim = min(idle)
             self.be.free(self.resident.pop(victim).obj)
+        if have is not None:
+            return have
         mesh, kernel, kappa = key
         V, T = self.meshes[mesh]
         obj, real = self.be.build(V, T, kernel, kappa)
@@ -601,7 +604,14 @@ class H2Server:
             "throughput_req_s": len(done) / span if span > 0 else None,
             "rhs_solved": int(sum(q.b.shape[0] for q in done)),
             "ticks": self.ticks, "batched_products": self.batched_products,
+            "errors": dict(Counter(q.error for q in self.finished if q.status in ("failed", "cancelled"))),
         }
+
+    def failures(self) -> List[dict]:
+        """What each failed request was and why (mesh, kernel, width, iterations)."""
+        return [{"rid": q.rid, "mesh": q.mesh, "kernel": q.kernel, "kappa": q.kappa, "rhs": int(q.b.shape[0]),
+                 "iterations": q.iterations, "products": q.products, "error": q.error}
+                for q in self.finished if q.status == "failed"]
 
 
 class _nullcontext:

@@ -223,3 +223,31 @@ def test_non_convergence_and_poisoned_products():
     p = P.submit("sphere1", np.ones(80), rtol=1e-8)
     P.run()
     assert p.status == "failed" and "non-finite" in p.error
+
+
+def test_resident_structure_makes_room_for_request_vectors():
+    """A request whose structure is already resident evicts other idle
+    structures when its vectors would not fit beside them."""
+    be = DenseBackend()
+    n1 = I.icosphere(1)[1].shape[0]
+    n2 = I.icosphere(2)[1].shape[0]
+    v2 = 8 * n2 * 8                       # vectors of a one-column CG request on sphere2
+    budget = n2 * n2 * 8 + n1 * n1 * 8 + v2 // 2
+    S = make_server(be, budget=budget)
+    rng = np.random.default_rng(7)
+    a = S.submit("sphere2", rng.standard_normal(n2), rtol=1e-8, arrival=0.0)
+    b = S.submit("sphere1", rng.standard_normal(n1), rtol=1e-8, arrival=1.0)
+    c = S.submit("sphere2", rng.standard_normal(n2), rtol=1e-8, arrival=2.0)
+    S.run()
+    assert [q.status for q in (a, b, c)] == ["done"] * 3, S.stats()["errors"]
+    assert be.built == 2 and be.freed == 1          # sphere1 evicted, sphere2 kept
+    assert S.stats()["errors"] == {}
+
+
+def test_failures_are_reported():
+    S = make_server(DenseBackend())
+    S.submit("nope", np.ones(10))
+    S.run()
+    assert S.stats()["errors"] == {"unknown mesh 'nope'": 1}
+    (f,) = S.failures()
+    assert f["mesh"] == "nope" and f["error"].startswith("unknown mesh")
