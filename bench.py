@@ -32,6 +32,14 @@ WORKLOADS = {
     "sphere327k_m4_f64": ("sphere", 7, 4, 64, "f64", 2),
     "cube786k_m4_f32": ("cube", 256, 4, 64, "f32", 4),
 }
+# the same products with the coupling matrices evaluated during the product
+OTF_WORKLOADS = {"sphere1310k_m4_f32_otf": "sphere1310k_m4_f32", "sphere1310k_m4_f64_otf": "sphere1310k_m4_f64"}
+# Peak rate of the on-the-fly coupling kernel in coupling entries per second:
+# each entry takes two FP32 FMAs (64 lanes per CU per clock; packed FP32 is not
+# used) and one v_rsq_f32, which issues at half that rate on gfx950 (32 lanes per
+# CU per clock, measured with a throughput probe), so 2/64 + 1/32 CU clocks per
+# entry on 256 CUs at 2.4 GHz.
+OTF_F32_PEAK_TENTRY = 256 * 2.4e9 / (2.0 / 64 + 1.0 / 32) / 1e12
 # many right-hand sides: (mesh kind, level, order, leaf, storage, seed, nrhs)
 MULTI = {"cube786k_m4_r64": ("cube", 256, 4, 64, "f32", 4, 64)}
 MFMA_F32_PEAK_TFS = 157.3
@@ -55,6 +63,34 @@ def measure(A, x, y, steps, warmup, torch, h2):
     prof = h2.h2_profile_read(A.h)
     h2.h2_profile(A.h, False)
     return el, prof
+
+
+def graph_timing(A, x, y, torch, reps=20, warmup=5):
+    """Median and p90 of single products replayed from a captured HIP graph,
+    each timed with HIP events on the replay stream."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        A.matvec(x, y)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        A.matvec(x, y)
+    for _ in range(warmup):
+        g.replay()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del g
+    ms.sort()
+    return {"replays": reps, "median_ms": ms[len(ms) // 2], "p90_ms": ms[int(0.9 * (len(ms) - 1))],
+            "matvec_per_s_median": 1e3 / ms[len(ms) // 2]}
 
 
 def cpu_baseline_sample(kind, level, order, leaf, seed, budget_s=25.0):
@@ -162,6 +198,17 @@ def recorded_traffic(workload):
     if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != mh.group(1):
         return None
     return float(mt.group(1))
+
+
+def otf_roofline(info, coup_avg_ms, storage):
+    """Roofline of the on-the-fly coupling kernel: bound by vector ALU issue
+    (FP32: the peak derived above; FP64: no peak figure is claimed)."""
+    entries = float(info["n_adm"]) * info["k"] ** 2
+    achieved = entries / (coup_avg_ms * 1e-3) / 1e12
+    peak = OTF_F32_PEAK_TENTRY if storage == "f32" else None
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tentry/s",
+            "frac": achieved / peak if peak else None, "traffic": None, "kernel": "coupling64_otf",
+            "entries_per_launch": entries, "avg_launch_ms": coup_avg_ms}
 
 
 def _walk(c):
@@ -277,6 +324,7 @@ def bench_serve(args):
                    "arrival_rate_per_s": args.serve_rate, "rtol": 1e-8, "slots": args.serve_slots,
                    "storage": "f32 (FP64 iterative refinement)"},
         "serving": dict(st, build_s=build_s, span_s=span, resident_GB=S.used_bytes() / 1e9,
+                        failures=S.failures()[:20],
                         iterations_mean=float(np.mean([q.iterations for q in S.finished])),
                         iterations_by_kernel={k: float(np.mean([q.iterations for q in S.finished if q.kernel == k]))
                                               for k in ("laplace", "helmholtz")},
@@ -293,15 +341,18 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere1310k_m4_f32",
-                    choices=sorted(WORKLOADS) + sorted(MULTI) + ["serve_mix"])
+                    choices=sorted(WORKLOADS) + sorted(OTF_WORKLOADS) + sorted(MULTI) + ["serve_mix"])
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-budget-gb", type=float, default=220.0)
     ap.add_argument("--serve-deadline-s", type=float, default=150.0, help="cancel what is unfinished after this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison run")
+    ap.add_argument("--no-solve", "--no-fp64", dest="no_solve", action="store_true",
+                    help="skip the solve comparison (FP64 vs mixed precision vs BF16 coupling)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a device copy of known size")
+    ap.add_argument("--no-otf", action="store_true",
+                    help="skip the variant with coupling matrices evaluated during the product")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the H^2 product here runs on a single MI355X "
@@ -318,12 +369,14 @@ def main():
         return bench_multi(args)
     if args.workload == "serve_mix":
         return bench_serve(args)
-    kind, level, order, leaf, storage, seed = WORKLOADS[args.workload]
+    otf = args.workload in OTF_WORKLOADS
+    kind, level, order, leaf, storage, seed = WORKLOADS[OTF_WORKLOADS.get(args.workload, args.workload)]
     V, T = I.mesh_for(kind, level)
     n = T.shape[0]
-    log("bench: %s n=%d m=%d leaf=%d storage=%s" % (args.workload, n, order, leaf, storage))
+    log("bench: %s n=%d m=%d leaf=%d storage=%s%s" % (args.workload, n, order, leaf, storage,
+                                                      " coupling on the fly" if otf else ""))
     t0 = time.perf_counter()
-    A = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
+    A = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage, coupling_otf=otf)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = A.info
@@ -338,6 +391,11 @@ def main():
     coup_ms, coup_calls = prof["coupling"]
     coup_avg_ms = coup_ms / max(1, coup_calls)
     achieved = coup_bytes / (coup_avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.workload),
+            "kernel": "coupling64", "algorithmic_bytes_per_launch": coup_bytes, "avg_launch_ms": coup_avg_ms}
+    if otf:
+        roof = otf_roofline(info, coup_avg_ms, storage)
     log("bench: %.3f ms/matvec; phases %s" % (ms_step, {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()}))
     out = {
         "metric": "H2 matvecs/s", "value": args.steps / el, "unit": "matvec/s", "n_gpus": 1,
@@ -346,11 +404,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "mesh": "%s level %d" % (kind, level), "triangles": n,
                    "order_m": order, "k": order ** 3, "leaf": leaf, "eta": 0.5, "storage": storage,
-                   "accumulate": "f64" if storage == "f64" else "f32", "rhs": 1},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.workload),
-                     "kernel": "coupling64",
-                     "algorithmic_bytes_per_launch": coup_bytes, "avg_launch_ms": coup_avg_ms},
+                   "accumulate": "f64" if storage == "f64" else "f32", "rhs": 1,
+                   "coupling": "evaluated during the product" if otf else "stored"},
+        "roofline": roof,
         "path": {"algorithmic_bytes": info["matvec_bytes"],
                  "achieved_GBs": info["matvec_bytes"] / (el / args.steps) / 1e9,
                  "frac_hbm_peak": info["matvec_bytes"] / (el / args.steps) / 1e9 / HBM_PEAK_GBS,
@@ -359,20 +415,60 @@ def main():
                  "n_adm": info["n_adm"], "n_near": info["n_near"], "near_entries": info["near_entries"],
                  "nclusters": info["nclusters"]},
     }
+    try:
+        out["graph_replay"] = graph_timing(A, x, y, torch)
+    except Exception as e:  # a report, never a reason to lose the line
+        out["graph_replay"] = {"error": repr(e)}
     A.close()
     del A
     torch.cuda.empty_cache()
-    if not args.no_fp64 and storage != "f64":
-        log("bench: FP64-storage comparison")
-        B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage="f64")
-        y64 = torch.zeros_like(x)
-        el64, prof64 = measure(B, x, y64, max(3, args.steps // 2), 1, torch, h2)
-        st64 = max(3, args.steps // 2)
-        out["fp64_compare"] = {"value": st64 / el64, "unit": "matvec/s",
-                               "algorithmic_bytes": B.info["matvec_bytes"],
-                               "frac_hbm_peak": B.info["matvec_bytes"] / (el64 / st64) / 1e9 / HBM_PEAK_GBS,
-                               "speedup_f32_over_f64": (args.steps / el) / (st64 / el64)}
+    if not otf and not args.no_otf and storage in ("f32", "f64"):
+        log("bench: variant with the coupling evaluated during the product")
+        B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage, coupling_otf=True)
+        yb = torch.zeros_like(x)
+        elb, profb = measure(B, x, yb, args.steps, args.warmup, torch, h2)
+        cb = profb["coupling"][0] / max(1, profb["coupling"][1])
+        out["otf_variant"] = {"value": args.steps / elb, "unit": "matvec/s", "ms_per_step": 1e3 * elb / args.steps,
+                              "device_bytes": B.info["bytes_total"],
+                              "phase_ms": {k: v[0] / max(1, v[1]) for k, v in profb.items()},
+                              "roofline": otf_roofline(B.info, cb, storage)}
         B.close()
+        del B
+        torch.cuda.empty_cache()
+    if not args.no_solve:
+        # time to a 1e-8 solve, b_i = |T_i| (z ~ 1 on the unit sphere), CG
+        P = V[T]
+        area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+        bd = torch.tensor(area, dtype=torch.float64, device="cuda")
+        solves = {}
+        for st_name in (["f64", storage] if storage != "f64" else ["f64"]) + (["f32_sbf16"] if storage == "f32" else []):
+            log("bench: solve with %s storage" % st_name)
+            M = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=st_name)
+            yy = torch.zeros_like(x)
+            elv, _ = measure(M, x, yy, max(3, args.steps // 2), 1, torch, h2)
+            mv = max(3, args.steps // 2) / elv
+            z = torch.zeros_like(bd)
+            torch.cuda.synchronize()
+            info_s = h2.h2_solve(M.h, bd, z, method="cg", rtol=1e-8, maxit=2000, refine=st_name != "f64",
+                                 inner_rtol=1e-4, check=False)
+            torch.cuda.synchronize()
+            zz = z.cpu().numpy()
+            solves[st_name] = dict(info_s, matvec_per_s=mv, matvec_bytes=M.info["matvec_bytes"],
+                                   frac_hbm_peak=M.info["matvec_bytes"] * mv / 1e9 / HBM_PEAK_GBS,
+                                   z_minus_1_rms=float(np.sqrt(np.mean((zz - 1.0) ** 2))))
+            if st_name == "f64":
+                z64 = zz
+            else:
+                solves[st_name]["rel_diff_to_f64_solution"] = float(np.linalg.norm(zz - z64) / np.linalg.norm(z64))
+            M.close()
+            del M
+            torch.cuda.empty_cache()
+        out["solve_compare"] = solves
+        if "f64" in solves and storage in solves and storage != "f64":
+            out["fp64_compare"] = {"value": solves["f64"]["matvec_per_s"], "unit": "matvec/s",
+                                   "speedup_f32_over_f64": solves[storage]["matvec_per_s"] / solves["f64"]["matvec_per_s"],
+                                   "time_to_1e-8_f64_s": solves["f64"]["seconds"],
+                                   "time_to_1e-8_mixed_s": solves[storage]["seconds"]}
     if args.copy_probe:
         out["copy_probe"] = copy_probe(torch)
     if not args.no_cpu_baseline:

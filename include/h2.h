@@ -78,7 +78,12 @@ extern "C" {
 #define H2_ACC_F64 1 /* accumulate in FP64 even when the matrix is stored in FP32/BF16 */
 
 /* h2_params.flags */
-#define H2_HOST_ONLY 1 /* build only the trees (no device work); for structure inspection */
+#define H2_HOST_ONLY 1   /* build only the trees (no device work); for structure inspection */
+#define H2_COUPLING_OTF 2 /* do not store the coupling matrices: every product evaluates
+                             s_{nu mu} = g(xi_{tau,nu}, xi_{sigma,mu}) (eq. coupling) from the
+                             clusters' interpolation points.  Real kernels only; FP64 storage
+                             evaluates in FP64, FP32 storage in FP32 from FP64 cluster-centre
+                             differences plus FP32 offsets. */
 
 typedef struct h2_handle_s* h2_handle;
 

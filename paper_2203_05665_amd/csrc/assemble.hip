@@ -383,7 +383,7 @@ void assemble_typed(h2_handle_s& H) {
   H.Vb.alloc(n * k * sizeof(VT));
   H.F.alloc(nc * kk * sizeof(VT));
   H.ET.alloc(nc * kk * sizeof(VT));
-  H.Smat.alloc(static_cast<int64_t>(S.adm_col.size()) * kk * cw * sizeof(SST));
+  H.Smat.alloc(H.otf ? 16 : static_cast<int64_t>(S.adm_col.size()) * kk * cw * sizeof(SST));
   H.Nmat.alloc(S.near_entries * cw * sizeof(VT));
   H2_HIP(hipMemset(H.F.p, 0, H.F.bytes));
   H2_HIP(hipMemset(H.ET.p, 0, H.ET.bytes));
@@ -413,7 +413,7 @@ void assemble_typed(h2_handle_s& H) {
 
   // coupling: row index of every admissible block
   const int64_t nadm = static_cast<int64_t>(S.adm_col.size());
-  if (nadm > 0) {
+  if (nadm > 0 && !H.otf) {
     std::vector<int32_t> row(nadm);
     for (int32_t c = 0; c < S.nclusters; ++c)
       for (int64_t b = S.adm_ptr[c]; b < S.adm_ptr[c + 1]; ++b) row[b] = c;
@@ -526,7 +526,28 @@ void assemble_typed(h2_handle_s& H) {
 }  // namespace
 
 void assemble(h2_handle_s& H) {
-  H.pts.upload(cluster_points(H.S));
+  const std::vector<double> pts = cluster_points(H.S);
+  H.pts.upload(pts);
+  if (H.otf) {
+    // centres of the (padded) point boxes and the offsets of the points from them
+    const Structure& S = H.S;
+    const int m = S.m;
+    std::vector<double> ctr(3 * static_cast<size_t>(S.nclusters)), o64(pts.size());
+    std::vector<float> o32(pts.size());
+    for (int32_t c = 0; c < S.nclusters; ++c)
+      for (int d = 0; d < 3; ++d) {
+        const double mid = 0.5 * (S.lo[3 * c + d] + S.hi[3 * c + d]);
+        ctr[3 * c + d] = mid;
+        for (int j = 0; j < m; ++j) {
+          const size_t i = (static_cast<size_t>(c) * 3 + d) * m + j;
+          o64[i] = pts[i] - mid;
+          o32[i] = static_cast<float>(o64[i]);
+        }
+      }
+    H.ctr.upload(ctr);
+    H.off64.upload(o64);
+    H.off32.upload(o32);
+  }
   if (H.is_complex) {
     if (H.P.storage == H2_F64) assemble_typed<double, double, true>(H);
     else assemble_typed<float, float, true>(H);

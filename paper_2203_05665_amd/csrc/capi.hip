@@ -103,6 +103,9 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
       H->P = P;
       H->host_only = (P.flags & H2_HOST_ONLY) != 0;
       H->is_complex = P.kernel == H2_HELMHOLTZ;
+      H->otf = (P.flags & H2_COUPLING_OTF) != 0;
+      if (H->otf && (H->is_complex || P.storage == H2_F32_SBF16))
+        throw h2::Error(H2_EINVAL, "on-the-fly coupling needs a real kernel and FP64 or FP32 storage");
       h2::build_structure(H->S, mesh->vertices, mesh->nv, mesh->triangles, mesh->nt, P.order_m, P.leaf_size,
                           P.eta);
       if (!H->host_only) {
@@ -192,7 +195,7 @@ int h2_info(h2_handle h, h2_stats* out) {
     const double sb = h->P.storage == H2_F64 ? 8.0 : (h->P.storage == H2_F32 ? 4.0 : 2.0);
     const double k = S.k;
     const double v_e = 2.0 * S.n * k + 2.0 * k * k * (S.nclusters - 1);
-    out->matvec_bytes = vb * v_e + cw * (sb * k * k * out->n_adm + vb * static_cast<double>(S.near_entries));
+    out->matvec_bytes = vb * v_e + cw * ((h->otf ? 0.0 : sb * k * k * out->n_adm) + vb * static_cast<double>(S.near_entries));
     out->matvec_flops = 2.0 * (v_e * (h->is_complex ? 2.0 : 1.0) +
                                (h->is_complex ? 4.0 : 1.0) * (k * k * out->n_adm + static_cast<double>(S.near_entries)));
     return H2_OK;
@@ -273,6 +276,7 @@ int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap) {
       }
     };
     std::vector<double> v;
+    if (what == H2_X_S && h->otf) return fail(H2_EINVAL, "coupling matrices are not stored (H2_COUPLING_OTF)");
     if (what == H2_X_V) {
       if (index < 0 || index >= nc || S.child0[index] >= 0) return fail(H2_EINVAL, "not a leaf cluster");
       const int64_t b0 = S.cbegin[index], r = S.cend[index] - b0;

@@ -65,12 +65,16 @@ struct h2_handle_s {
   h2_params P{};
   bool host_only = false;
   bool is_complex = false;
+  bool otf = false;       // coupling matrices evaluated during the product
   int device = 0;
   size_t val_bytes = 8;   // bytes per stored real scalar of V, E, N
   size_t s_bytes = 8;     // bytes per stored real scalar of S
   // device structure
   h2::DBuf perm, cbegin, cend, parent, child0, child1, leaves, adm_ptr, adm_col, near_ptr, near_col,
       panel_off, up_list, pts;
+  // on-the-fly coupling: cluster centres (FP64, 3 per cluster) and point offsets from
+  // the centre (3 x m per cluster, FP32 and FP64)
+  h2::DBuf ctr, off32, off64;
   std::vector<int64_t> up_ptr;  // host offsets into up_list per level
   // matrix data
   h2::DBuf Vf, Vb, F, ET, Smat, Nmat;

@@ -279,6 +279,150 @@ __global__ __launch_bounds__(256) void coupling_any(int nc, int k, const int64_t
   }
 }
 
+// ---------------------------------------------------------------- coupling evaluated on the fly
+// s_{nu mu} = g(xi_{tau,nu}, xi_{sigma,mu}) (eq. coupling) from the tensor
+// Chebyshev points: xi - eta = (c_tau - c_sigma) + (o_tau - o_sigma) per axis,
+// with the centre difference formed in FP64 and the small offsets o in the
+// evaluation precision ET, so the difference keeps ET's relative accuracy even
+// for clusters far from the origin.
+__device__ inline float rsq(float v) { return __frsqrt_rn(v); }
+__device__ inline double rsq(double v) { return rsqrt(v); }
+
+template <int KIND, typename ET>
+__device__ inline ET otf_g(ET dx, ET dy, ET dz, ET x0, ET x1, ET x2, ET y0, ET y1, ET y2) {
+  if (KIND == H2_LAPLACE) return rsq(dx * dx + dy * dy + dz * dz);  // times 1/(4 pi) at the end
+  if (KIND == H2_TEST_ONE) return ET(1);
+  const ET d = x0 * y0 + x1 * y1 + x2 * y2;
+  if (KIND == H2_TEST_BILINEAR) return d;
+  return d * d;
+}
+
+// k = 64 (m = 4): one 256-thread workgroup per row cluster tau.  Wave w takes
+// the blocks ptr[tau] + w, + 4, ...; lane nu owns row nu and all 64 columns of
+// each of its blocks.  What depends on the column cluster only (its centre, its
+// 12 point offsets, x^_sigma) is the same for the whole wave and is read with
+// wave-uniform loads; per entry a lane then needs one add, one reciprocal
+// square root and one FMA.  The four wave partials are summed through LDS in a
+// fixed order, so the result is reproducible.
+template <int KIND, typename ET, typename AT>
+__global__ __launch_bounds__(256) void coupling64_otf(int nc, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ ctr, const ET* __restrict__ off,
+                                                      const AT* __restrict__ xhat, AT* __restrict__ yhat) {
+  __shared__ AT part[3][64];
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int nu = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const ET* ot = off + static_cast<int64_t>(tau) * 12;
+  const ET ax = ot[nu & 3], ay = ot[4 + ((nu >> 2) & 3)], az = ot[8 + (nu >> 4)];
+  const double cx = ctr[3 * tau], cy = ctr[3 * tau + 1], cz = ctr[3 * tau + 2];
+  AT acc = 0;
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau] + w; b < b1; b += 4) {
+    const int64_t s = col[b];
+    const ET* os = off + s * 12;
+    const AT* xs = xhat + s * 64;
+    if (KIND == H2_LAPLACE) {
+      const ET ex = static_cast<ET>(cx - ctr[3 * s]) + ax, ey = static_cast<ET>(cy - ctr[3 * s + 1]) + ay,
+               ez = static_cast<ET>(cz - ctr[3 * s + 2]) + az;
+      ET dx2[4], dy2[4], dz2[4], dyz[16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const ET dx = ex - os[i], dy = ey - os[4 + i], dz = ez - os[8 + i];
+        dx2[i] = dx * dx;
+        dy2[i] = dy * dy;
+        dz2[i] = dz * dz;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dyz[i] = dy2[i & 3] + dz2[i >> 2];
+#pragma unroll
+      for (int j = 0; j < 64; ++j) acc += static_cast<AT>(rsq(dx2[j & 3] + dyz[j >> 2])) * xs[j];
+    } else {
+      // polynomial test kernels on absolute coordinates
+      const ET x0 = static_cast<ET>(cx) + ax, x1 = static_cast<ET>(cy) + ay, x2 = static_cast<ET>(cz) + az;
+      ET px[4], pyz[16], py[4], pz[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        px[i] = x0 * (static_cast<ET>(ctr[3 * s]) + os[i]);
+        py[i] = x1 * (static_cast<ET>(ctr[3 * s + 1]) + os[4 + i]);
+        pz[i] = x2 * (static_cast<ET>(ctr[3 * s + 2]) + os[8 + i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) pyz[i] = py[i & 3] + pz[i >> 2];
+#pragma unroll
+      for (int j = 0; j < 64; ++j) {
+        const ET d = px[j & 3] + pyz[j >> 2];
+        const ET g = KIND == H2_TEST_ONE ? ET(1) : KIND == H2_TEST_BILINEAR ? d : d * d;
+        acc += static_cast<AT>(g) * xs[j];
+      }
+    }
+  }
+  if (w > 0) part[w - 1][nu] = acc;
+  __syncthreads();
+  if (w == 0) {
+    acc = ((acc + part[0][nu]) + part[1][nu]) + part[2][nu];
+    const AT scale = KIND == H2_LAPLACE ? AT(1.0 / (4.0 * 3.14159265358979323846)) : AT(1);
+    yhat[static_cast<int64_t>(tau) * 64 + nu] = acc * scale;
+  }
+}
+
+// any order m: one thread per row nu
+template <int KIND, typename ET, typename AT>
+__global__ __launch_bounds__(256) void coupling_any_otf(int nc, int m, const int64_t* __restrict__ ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ ctr, const ET* __restrict__ off,
+                                                        const AT* __restrict__ xhat, AT* __restrict__ yhat) {
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int k = m * m * m;
+  const ET* ot = off + static_cast<int64_t>(tau) * 3 * m;
+  for (int nu = threadIdx.x; nu < k; nu += blockDim.x) {
+    const ET ax = ot[nu % m], ay = ot[m + (nu / m) % m], az = ot[2 * m + nu / (m * m)];
+    AT acc = 0;
+    for (int64_t b = ptr[tau]; b < ptr[tau + 1]; ++b) {
+      const int64_t s = col[b];
+      const ET* os = off + s * 3 * m;
+      const ET dcx = static_cast<ET>(ctr[3 * tau] - ctr[3 * s]), dcy = static_cast<ET>(ctr[3 * tau + 1] - ctr[3 * s + 1]),
+               dcz = static_cast<ET>(ctr[3 * tau + 2] - ctr[3 * s + 2]);
+      for (int mu = 0; mu < k; ++mu) {
+        const ET ox = os[mu % m], oy = os[m + (mu / m) % m], oz = os[2 * m + mu / (m * m)];
+        const ET x0 = static_cast<ET>(ctr[3 * tau]) + ax, x1 = static_cast<ET>(ctr[3 * tau + 1]) + ay,
+                 x2 = static_cast<ET>(ctr[3 * tau + 2]) + az;
+        const ET y0 = static_cast<ET>(ctr[3 * s]) + ox, y1 = static_cast<ET>(ctr[3 * s + 1]) + oy,
+                 y2 = static_cast<ET>(ctr[3 * s + 2]) + oz;
+        const ET g = otf_g<KIND, ET>((dcx + ax) - ox, (dcy + ay) - oy, (dcz + az) - oz, x0, x1, x2, y0, y1, y2);
+        acc += static_cast<AT>(g) * xhat[s * k + mu];
+      }
+    }
+    const AT scale = KIND == H2_LAPLACE ? AT(1.0 / (4.0 * 3.14159265358979323846)) : AT(1);
+    yhat[static_cast<int64_t>(tau) * k + nu] = acc * scale;
+  }
+}
+
+template <typename ET, typename AT>
+void launch_otf(h2_handle_s& H, const AT* xh, AT* yh, hipStream_t st) {
+  const Structure& S = H.S;
+  const int nc = S.nclusters;
+  const ET* off = static_cast<const ET*>(sizeof(ET) == 8 ? H.off64.p : H.off32.p);
+  const double* ctr = H.ctr.as<double>();
+  const int64_t* ptr = H.adm_ptr.as<int64_t>();
+  const int32_t* col = H.adm_col.as<int32_t>();
+#define H2_OTF_CASE(K)                                                                                \
+  case K:                                                                                             \
+    if (S.k == 64) coupling64_otf<K, ET, AT><<<nc, 256, 0, st>>>(nc, ptr, col, ctr, off, xh, yh);    \
+    else coupling_any_otf<K, ET, AT><<<nc, 256, 0, st>>>(nc, S.m, ptr, col, ctr, off, xh, yh);       \
+    break;
+  switch (H.P.kernel) {
+    H2_OTF_CASE(H2_LAPLACE)
+    H2_OTF_CASE(H2_TEST_ONE)
+    H2_OTF_CASE(H2_TEST_BILINEAR)
+    H2_OTF_CASE(H2_TEST_QUADRATIC)
+    default: throw Error(H2_EINVAL, "on-the-fly coupling supports real kernels only");
+  }
+#undef H2_OTF_CASE
+}
+
 // ---------------------------------------------------------------- near field + leaf backward
 // one 256-thread workgroup per row leaf tau; lane = row of tau.  The near blocks
 // of the row are dealt round-robin to the four waves; a wave stages x|sigma one
@@ -560,12 +704,16 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
   }
-  if (k == 64)
+  if (H.otf) {
+    if (H.P.storage == H2_F64) launch_otf<double, AT>(H, xh, yh, st);
+    else launch_otf<float, AT>(H, xh, yh, st);
+  } else if (k == 64) {
     coupling64<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<SST>(),
                                            xh, yh);
-  else
+  } else {
     coupling_any<SST, AT><<<nc, 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
                                              H.Smat.as<SST>(), xh, yh);
+  }
   if (H.prof) {
     e2 = prof_event(H);
     H2_HIP(hipEventRecord(e2, st));

@@ -209,3 +209,40 @@ def test_multi_rhs_matches_oracle(case, nrhs):
         ref = Y0[:, j] + 0.5 * H.matvec(X[:, j])
         scale = 0.5 * H.matvec(np.abs(X[:, j]))
         assert np.linalg.norm(Y[:, j] - ref) <= 1e-6 * np.linalg.norm(scale), j
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", [("sphere", 3, 3, 32), ("sphere", 3, 4, 16), ("cube", 16, 4, 32),
+                                  ("sphere", 2, 5, 40)])
+def test_on_the_fly_coupling_matches_oracle(case, storage):
+    """Coupling matrices evaluated during the product (not stored) give the
+    same product as the oracle, to the tolerance of the storage precision."""
+    kind, level, m, leaf = case
+    H = oracle(kind, level, m, leaf)
+    x = I.random_vector(H.mesh.n, 1, "uniform")
+    ref = H.matvec(x)
+    ref_abs = H.matvec(np.abs(x))
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage=storage, coupling_otf=True)
+    try:
+        assert A.info["bytes_S"] <= 16
+        y = gpu_matvec(A, x)
+        assert err(storage, y, ref, ref_abs) <= TOL[storage]
+        if storage == "f32":
+            assert err(storage, gpu_matvec(A, x, acc64=True), ref, ref_abs) <= TOL[storage]
+        with pytest.raises(h2.H2Error):
+            A.export(h2.H2_X_S, 0)
+    finally:
+        A.close()
+
+
+@pytest.mark.parametrize("kernel,m,name", [("one", 1, "one"), ("bilinear", 2, "bilinear"),
+                                           ("quadratic", 4, "quadratic")])
+def test_on_the_fly_closed_forms(kernel, m, name):
+    V, T = I.mesh_for("sphere", 6)
+    x = I.random_vector(T.shape[0], 5, "normal")
+    ref = poly_kernel_product(V, T, name, x)
+    A = h2.H2Matrix(V, T, kernel=kernel, order=m, leaf=64, eta=0.5, storage="f64", coupling_otf=True)
+    try:
+        assert rel(gpu_matvec(A, x), ref) <= 1e-12
+    finally:
+        A.close()
