@@ -102,7 +102,7 @@ typedef struct {
   double eta;     /* admissibility parameter of eq. admissibility             */
   int q_ss;       /* Gauss-Legendre order per axis of the Sauter-Schwab rules */
   int storage;    /* H2_F64, H2_F32, H2_F32_SBF16                             */
-  int flags;      /* H2_HOST_ONLY or 0                                        */
+  int flags;      /* 0, or H2_HOST_ONLY and/or H2_COUPLING_OTF                */
 } h2_params;
 
 typedef struct {

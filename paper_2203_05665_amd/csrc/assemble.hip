@@ -151,6 +151,22 @@ __global__ void asm_transfer(int nc, int k, int m, const int32_t* __restrict__ p
   store(ET + c * kk + static_cast<int64_t>(nu) * k + nup, v);
 }
 
+// one-dimensional factors of the transfer matrices: the Lagrange polynomials
+// are tensor products, so E_c[nu'][nu] = prod_d l_{nu_d}(xi_{nu'_d}) (eq. transfer)
+template <typename ST>
+__global__ void asm_transfer1d(int nc, int m, const int32_t* __restrict__ parent, const double* __restrict__ pts,
+                               ST* __restrict__ E1) {
+  const int64_t mm3 = 3 * static_cast<int64_t>(m) * m;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nc * mm3) return;
+  const int64_t c = e / mm3;
+  const int rem = static_cast<int>(e % mm3);
+  const int d = rem / (m * m), i = (rem / m) % m, j = rem % m;
+  double v = 0.0;
+  if (c > 0) v = lagrange1(pts + static_cast<int64_t>(parent[c]) * 3 * m + d * m, m, j, pts[c * 3 * m + d * m + i]);
+  store(E1 + e, v);
+}
+
 // ---------------------------------------------------------------- coupling matrices
 template <typename ST, bool CPLX>
 __global__ void asm_coupling(int64_t nblocks, int k, int m, KernelFn kf, const int32_t* __restrict__ row,
@@ -409,6 +425,10 @@ void assemble_typed(h2_handle_s& H) {
   H2_HIP(hipGetLastError());
   asm_transfer<VT><<<grid_for(nc * kk, 256), 256>>>(static_cast<int>(nc), k, m, H.parent.as<int32_t>(),
                                                     H.pts.as<double>(), H.F.as<VT>(), H.ET.as<VT>());
+  H2_HIP(hipGetLastError());
+  H.E1.alloc(nc * 3 * m * m * sizeof(VT));
+  asm_transfer1d<VT><<<grid_for(nc * 3 * m * m, 256), 256>>>(static_cast<int>(nc), m, H.parent.as<int32_t>(),
+                                                             H.pts.as<double>(), H.E1.as<VT>());
   H2_HIP(hipGetLastError());
 
   // coupling: row index of every admissible block

@@ -188,13 +188,15 @@ int h2_info(h2_handle h, h2_stats* out) {
     out->bytes_S = static_cast<int64_t>(h->Smat.bytes);
     out->bytes_N = static_cast<int64_t>(h->Nmat.bytes);
     out->bytes_V = static_cast<int64_t>(h->Vf.bytes + h->Vb.bytes);
-    out->bytes_E = static_cast<int64_t>(h->F.bytes + h->ET.bytes);
+    out->bytes_E = static_cast<int64_t>(h->F.bytes + h->ET.bytes + h->E1.bytes);
     out->bytes_total = out->bytes_S + out->bytes_N + out->bytes_V + out->bytes_E;
     const double cw = h->is_complex ? 2.0 : 1.0;
     const double vb = h->P.storage == H2_F64 ? 8.0 : 4.0;
     const double sb = h->P.storage == H2_F64 ? 8.0 : (h->P.storage == H2_F32 ? 4.0 : 2.0);
     const double k = S.k;
-    const double v_e = 2.0 * S.n * k + 2.0 * k * k * (S.nclusters - 1);
+    // V twice; E twice, in Kronecker form (3 m^2 numbers per cluster) on the k = 64 path
+    const double e_per = S.k == 64 ? 3.0 * S.m * S.m : k * k;
+    const double v_e = 2.0 * S.n * k + 2.0 * e_per * (S.nclusters - 1);
     out->matvec_bytes = vb * v_e + cw * ((h->otf ? 0.0 : sb * k * k * out->n_adm) + vb * static_cast<double>(S.near_entries));
     out->matvec_flops = 2.0 * (v_e * (h->is_complex ? 2.0 : 1.0) +
                                (h->is_complex ? 4.0 : 1.0) * (k * k * out->n_adm + static_cast<double>(S.near_entries)));

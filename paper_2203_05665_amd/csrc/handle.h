@@ -78,6 +78,9 @@ struct h2_handle_s {
   std::vector<int64_t> up_ptr;  // host offsets into up_list per level
   // matrix data
   h2::DBuf Vf, Vb, F, ET, Smat, Nmat;
+  // E_c = E_x (x) E_y (x) E_z: per cluster the three m x m one-dimensional factors,
+  // E1[c][d][i][j] = l_j(xi_i) along axis d (i child point, j parent polynomial)
+  h2::DBuf E1;
   // workspaces (sized for FP64 vectors, one right-hand side)
   h2::DBuf xc, yc, xhat, yhat;
   // many-right-hand-side workspaces (FP32, grown on first use)

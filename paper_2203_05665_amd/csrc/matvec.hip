@@ -202,6 +202,71 @@ __global__ __launch_bounds__(256) void transfer_down(int first, int count, int k
   }
 }
 
+// k = 64 (m = 4): E_c = E_x (x) E_y (x) E_z, applied one axis at a time.  One
+// wave per cluster, lane = nu = nu_x + 4 nu_y + 16 nu_z; each axis step
+// contracts four lanes that differ only in that axis (lane shuffles), so a
+// transfer reads 48 numbers instead of 4096.  E1 holds E1[c][d][i][j] =
+// l_j(xi_i) along axis d (i child point, j parent polynomial).
+template <typename ST, typename AT>
+__device__ inline AT kron_axis(AT t, const ST* __restrict__ e, int lane, int shift, bool transpose) {
+  const int own = (lane >> shift) & 3;
+  const int base = lane & ~(3 << shift);
+  AT r = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const AT v = __shfl(t, base | (i << shift));
+    // up (transpose): sum over child points i of E[i][own]; down: sum over parent polynomials i of E[own][i]
+    r += ld<ST, AT>(e + (transpose ? i * 4 + own : own * 4 + i)) * v;
+  }
+  return r;
+}
+
+// up: x^_c = sum over the two children a of E_a^T x^_a (Algorithm 1)
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void transfer_up_kron(int count, const int32_t* __restrict__ list,
+                                                        const int32_t* __restrict__ child0,
+                                                        const int32_t* __restrict__ child1,
+                                                        const ST* __restrict__ E1, AT* __restrict__ xhat) {
+  const int w = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (w >= count) return;
+  const int32_t c = list[w];
+  const int32_t ch[2] = {child0[c], child1[c]};
+  AT acc = 0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const ST* e = E1 + static_cast<int64_t>(ch[a]) * 48;
+    AT t = xhat[static_cast<int64_t>(ch[a]) * 64 + lane];
+    t = kron_axis<ST, AT>(t, e, lane, 0, true);
+    t = kron_axis<ST, AT>(t, e + 16, lane, 2, true);
+    t = kron_axis<ST, AT>(t, e + 32, lane, 4, true);
+    acc += t;
+  }
+  xhat[static_cast<int64_t>(c) * 64 + lane] = acc;
+}
+
+// down: y^_c += E_c y^_parent(c) (Algorithm 2)
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void transfer_down_kron(int first, int count, const int32_t* __restrict__ parent,
+                                                          const ST* __restrict__ E1, AT* __restrict__ yhat) {
+  const int w = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (w >= count) return;
+  const int64_t c = first + w;
+  const ST* e = E1 + c * 48;
+  AT t = yhat[static_cast<int64_t>(parent[c]) * 64 + lane];
+  t = kron_axis<ST, AT>(t, e, lane, 0, false);
+  t = kron_axis<ST, AT>(t, e + 16, lane, 2, false);
+  t = kron_axis<ST, AT>(t, e + 32, lane, 4, false);
+  yhat[c * 64 + lane] += t;
+}
+
+// the transfer phases of one product: Kronecker form for k = 64, dense otherwise
+template <typename ST, typename AT>
+void launch_up(h2_handle_s& H, AT* xh, hipStream_t st);
+template <typename ST, typename AT>
+void launch_down(h2_handle_s& H, AT* yh, hipStream_t st);
+
 // ---------------------------------------------------------------- coupling
 // k = 64 fast path: one 256-thread workgroup per row cluster; each thread reads
 // 16-byte vectors of S (lanes_per_row lanes cover one row of a block) and keeps
@@ -674,6 +739,37 @@ inline unsigned blocks_for(int64_t work, int per) {
   return static_cast<unsigned>(g < 1 ? 1 : g);
 }
 
+template <typename ST, typename AT>
+void launch_up(h2_handle_s& H, AT* xh, hipStream_t st) {
+  const Structure& S = H.S;
+  for (int l = S.depth - 1; l >= 0; --l) {
+    const int cnt = static_cast<int>(H.up_ptr[l + 1] - H.up_ptr[l]);
+    if (cnt == 0) continue;
+    const int32_t* list = H.up_list.as<int32_t>() + H.up_ptr[l];
+    if (S.k == 64)
+      transfer_up_kron<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, list, H.child0.as<int32_t>(),
+                                                                    H.child1.as<int32_t>(), H.E1.as<ST>(), xh);
+    else
+      transfer_up<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, S.k, list, H.child0.as<int32_t>(),
+                                                               H.child1.as<int32_t>(), H.F.as<ST>(), xh);
+  }
+}
+
+template <typename ST, typename AT>
+void launch_down(h2_handle_s& H, AT* yh, hipStream_t st) {
+  const Structure& S = H.S;
+  for (int l = 0; l < S.depth; ++l) {
+    const int first = S.level_ptr[l + 1], cnt = S.level_ptr[l + 2] - S.level_ptr[l + 1];
+    if (cnt == 0) continue;
+    if (S.k == 64)
+      transfer_down_kron<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(),
+                                                                      H.E1.as<ST>(), yh);
+    else
+      transfer_down<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, S.k, H.parent.as<int32_t>(),
+                                                                 H.ET.as<ST>(), yh);
+  }
+}
+
 template <typename SST, typename ST, typename AT, typename XT>
 void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t st) {
   const Structure& S = H.S;
@@ -693,13 +789,7 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
   permute_in<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), x, xc);
   leaf_forward<ST, AT><<<blocks_for(nl, 4), 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                                            H.cend.as<int32_t>(), H.Vf.as<ST>(), xc, xh);
-  for (int l = S.depth - 1; l >= 0; --l) {
-    const int cnt = static_cast<int>(H.up_ptr[l + 1] - H.up_ptr[l]);
-    if (cnt == 0) continue;
-    transfer_up<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, k, H.up_list.as<int32_t>() + H.up_ptr[l],
-                                                             H.child0.as<int32_t>(), H.child1.as<int32_t>(),
-                                                             H.F.as<ST>(), xh);
-  }
+  launch_up<ST, AT>(H, xh, st);
   if (H.prof) {
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
@@ -718,12 +808,7 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
     e2 = prof_event(H);
     H2_HIP(hipEventRecord(e2, st));
   }
-  for (int l = 0; l < S.depth; ++l) {
-    const int first = S.level_ptr[l + 1], cnt = S.level_ptr[l + 2] - S.level_ptr[l + 1];
-    if (cnt == 0) continue;
-    transfer_down<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, k, H.parent.as<int32_t>(), H.ET.as<ST>(),
-                                                               yh);
-  }
+  launch_down<ST, AT>(H, yh, st);
   if (H.prof) {
     e3 = prof_event(H);
     H2_HIP(hipEventRecord(e3, st));
@@ -781,13 +866,7 @@ void matvec_complex(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_
     leaf_forward<ST, AT><<<blocks_for(nl, 4), 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                                              H.cend.as<int32_t>(), H.Vf.as<ST>(), planes_x[pl],
                                                              planes_h[pl]);
-    for (int l = S.depth - 1; l >= 0; --l) {
-      const int cnt = static_cast<int>(H.up_ptr[l + 1] - H.up_ptr[l]);
-      if (cnt == 0) continue;
-      transfer_up<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, k, H.up_list.as<int32_t>() + H.up_ptr[l],
-                                                               H.child0.as<int32_t>(), H.child1.as<int32_t>(),
-                                                               H.F.as<ST>(), planes_h[pl]);
-    }
+    launch_up<ST, AT>(H, planes_h[pl], st);
   }
   if (H.prof) {
     e1 = prof_event(H);
@@ -804,13 +883,7 @@ void matvec_complex(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_
     H2_HIP(hipEventRecord(e2, st));
   }
   AT* planes_y[2] = {yhr, yhi};
-  for (int pl = 0; pl < 2; ++pl)
-    for (int l = 0; l < S.depth; ++l) {
-      const int first = S.level_ptr[l + 1], cnt = S.level_ptr[l + 2] - S.level_ptr[l + 1];
-      if (cnt == 0) continue;
-      transfer_down<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, k, H.parent.as<int32_t>(),
-                                                                 H.ET.as<ST>(), planes_y[pl]);
-    }
+  for (int pl = 0; pl < 2; ++pl) launch_down<ST, AT>(H, planes_y[pl], st);
   if (H.prof) {
     e3 = prof_event(H);
     H2_HIP(hipEventRecord(e3, st));

@@ -110,3 +110,30 @@ def test_laplace_sampled_rows_327k_dense_x():
     rows = np.concatenate([v[0] for v in ref.values()])
     val = np.concatenate([v[1] for v in ref.values()])
     assert err("f64", y[rows], val, None) <= 1e-12
+
+
+def test_multi_rhs_closed_form_cube786k():
+    """The many-right-hand-side (matrix-core) path in the configuration the
+    many-RHS benchmark times: 786,432-triangle cube, 64 columns, FP32 storage;
+    every column against the (x.y)^2 closed form, in the FP32 norm of that
+    column, and the block reproducible."""
+    print("multi-RHS closed form cube786k", flush=True)
+    V, T = I.mesh_for("cube", 256)
+    n, R = T.shape[0], 64
+    X = I.random_vector(n, 4, "normal", nrhs=R)
+    A = h2.H2Matrix(V, T, kernel="quadratic", order=4, leaf=64, eta=0.5, storage="f32")
+    try:
+        xd = torch.tensor(X, dtype=torch.float64, device="cuda").t().contiguous().t()
+        yd = torch.zeros_like(xd)
+        A.matvec(xd, yd)
+        y2 = torch.zeros_like(xd)
+        A.matvec(xd, y2)
+        torch.cuda.synchronize()
+        assert torch.equal(yd, y2)
+        Y = yd.cpu().numpy()
+    finally:
+        A.close()
+    for j in range(R):
+        ref = poly_kernel_product(V, T, "quadratic", X[:, j])
+        ref_abs = poly_kernel_product(V, T, "quadratic", np.abs(X[:, j]))
+        assert err("f32", Y[:, j], ref, ref_abs) <= TOL["f32"], j
