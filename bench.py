@@ -238,7 +238,10 @@ def bench_multi(args):
     Y = torch.zeros_like(X)
     el, prof = measure(A, X, Y, args.steps, args.warmup, torch, h2)
     k = info["k"]
-    flops_total = info["matvec_flops"] * R
+    # every step as a dense contraction over R columns: V twice, E twice (dense on
+    # this path), S, near field
+    flops_total = 2.0 * R * (2.0 * n * k + 2.0 * k * k * (info["nclusters"] - 1) + k * k * info["n_adm"]
+                             + info["near_entries"])
     coup_flops = 2.0 * k * k * info["n_adm"] * R
     coup_ms = prof["coupling"][0] / max(1, prof["coupling"][1])
     achieved = coup_flops / (coup_ms * 1e-3) / 1e12
@@ -256,6 +259,21 @@ def bench_multi(args):
                  "device_bytes": info["bytes_total"]},
     }
     A.close()
+    if not args.no_otf:
+        log("bench: many right-hand sides with the coupling evaluated during the product")
+        C = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage, coupling_otf=True)
+        Yc = torch.zeros_like(X)
+        elc, profc = measure(C, X, Yc, args.steps, args.warmup, torch, h2)
+        cms = profc["coupling"][0] / max(1, profc["coupling"][1])
+        out["otf_variant"] = {
+            "value": R * args.steps / elc, "unit": "rhs-matvec/s", "ms_per_step": 1e3 * elc / args.steps,
+            "phase_ms": {kk: v[0] / max(1, v[1]) for kk, v in profc.items()},
+            "device_bytes": C.info["bytes_total"],
+            "roofline": {"bound": "mfma", "achieved": coup_flops / (cms * 1e-3) / 1e12, "peak": MFMA_F32_PEAK_TFS,
+                         "unit": "TFLOP/s", "frac": coup_flops / (cms * 1e-3) / 1e12 / MFMA_F32_PEAK_TFS,
+                         "traffic": None, "kernel": "mcoupling_otf", "algorithmic_flops_per_launch": coup_flops,
+                         "avg_launch_ms": cms}}
+        C.close()
     # the same columns one at a time, for comparison
     B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
     x1 = X[:, 0].contiguous()

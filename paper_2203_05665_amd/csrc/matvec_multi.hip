@@ -251,6 +251,105 @@ __global__ __launch_bounds__(256) void mcoupling(int nc, const int64_t* __restri
   store_hat<NT, false>(yhat + tau * RP * 64, acc);
 }
 
+// The same with S evaluated on the fly (eq. coupling): every lane computes the
+// A-operand entries it feeds to the matrix cores instead of loading them, in the
+// K order of mma64_rowA (kk = 8 P + 4 h + e, P = 0..7): column point
+// mu = (e, (2 P + h) % 4, P / 2); rows nu = 32 ti + r = (r % 4, (r / 4) % 4,
+// 2 ti + r / 16).  Point differences are (c_tau - c_sigma) + (o_tau - o_sigma)
+// with FP64 centres and FP32 offsets, as in the single-vector kernel.
+template <int NT, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mcoupling_otf(int nc, const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col, const double* __restrict__ ctr,
+                                                     const float* __restrict__ off, const float* __restrict__ xhat,
+                                                     float* __restrict__ yhat) {
+  const int64_t tau = xcd_item(nc);
+  if (tau >= nc) return;
+  constexpr int RP = 32 * NT;
+  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+  const float* ot = off + tau * 12;
+  const float ax = ot[r % 4], ay = ot[4 + (r / 4) % 4];
+  const float az[2] = {ot[8 + r / 16], ot[10 + r / 16]};
+  const double cx = ctr[3 * tau], cy = ctr[3 * tau + 1], cz = ctr[3 * tau + 2];
+  f32x16 acc[2][NT];
+  zero(acc);
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau]; b < b1; ++b) {
+    const int64_t s = col[b];
+    const float* os = off + s * 12;
+    // per-axis parts: x by e, y by P & 1, z by (ti, P >> 1)
+    float px[4], py[2], pz[2][4];
+    if (KIND == H2_LAPLACE) {
+      const float ex = static_cast<float>(cx - ctr[3 * s]) + ax, ey = static_cast<float>(cy - ctr[3 * s + 1]) + ay;
+      const float dcz = static_cast<float>(cz - ctr[3 * s + 2]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float d = ex - os[e];
+        px[e] = d * d;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float d = ey - os[4 + 2 * j + h];
+        py[j] = d * d;
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int z = 0; z < 4; ++z) {
+          const float d = (dcz + az[ti]) - os[8 + z];
+          pz[ti][z] = d * d;
+        }
+    } else {  // polynomial test kernels: parts of x . y on absolute coordinates
+      const float x0 = static_cast<float>(cx) + ax, x1 = static_cast<float>(cy) + ay;
+      const float sx = static_cast<float>(ctr[3 * s]), sy = static_cast<float>(ctr[3 * s + 1]),
+                  sz = static_cast<float>(ctr[3 * s + 2]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) px[e] = x0 * (sx + os[e]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) py[j] = x1 * (sy + os[4 + 2 * j + h]);
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int z = 0; z < 4; ++z) pz[ti][z] = (static_cast<float>(cz) + az[ti]) * (sz + os[8 + z]);
+    }
+    const float* Bt = xhat + s * RP * 64;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      f4v bv[NT][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) bv[tj][q] = ld4c(Bt + (32 * tj + r) * 64 + 8 * (4 * half + q) + 4 * h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int P = 4 * half + q;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float a[2];
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti) {
+            const float t = px[e] + (py[P & 1] + pz[ti][P >> 1]);
+            a[ti] = KIND == H2_LAPLACE ? __builtin_amdgcn_rsqf(t)
+                    : KIND == H2_TEST_ONE ? 1.f
+                    : KIND == H2_TEST_BILINEAR ? t : t * t;
+          }
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma(a[ti], bv[tj][q][e], acc[ti][tj]);
+        }
+      }
+    }
+  }
+  if (KIND == H2_LAPLACE) {
+    const float scale = static_cast<float>(1.0 / (4.0 * 3.14159265358979323846));
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) acc[ti][tj] *= scale;
+  }
+  store_hat<NT, false>(yhat + tau * RP * 64, acc);
+}
+
 // y^_c += E_c y^_parent for the clusters of one level; A(nu', nu) = F[nu'][nu]
 template <int NT>
 __global__ __launch_bounds__(256) void mtransfer_down(int first, int count, const int32_t* __restrict__ parent,
@@ -589,8 +688,26 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
   }
-  mcoupling<NT><<<grid8(nc), 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<float>(),
-                                           xh, yh);
+  if (H.otf) {
+    const int64_t* ap = H.adm_ptr.as<int64_t>();
+    const int32_t* ac = H.adm_col.as<int32_t>();
+    const double* ctr = H.ctr.as<double>();
+    const float* off = H.off32.as<float>();
+    switch (H.P.kernel) {
+      case H2_LAPLACE: mcoupling_otf<NT, H2_LAPLACE><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh); break;
+      case H2_TEST_ONE: mcoupling_otf<NT, H2_TEST_ONE><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh); break;
+      case H2_TEST_BILINEAR:
+        mcoupling_otf<NT, H2_TEST_BILINEAR><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh);
+        break;
+      case H2_TEST_QUADRATIC:
+        mcoupling_otf<NT, H2_TEST_QUADRATIC><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh);
+        break;
+      default: throw Error(H2_EINVAL, "on-the-fly coupling supports real kernels only");
+    }
+  } else {
+    mcoupling<NT><<<grid8(nc), 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
+                                             H.Smat.as<float>(), xh, yh);
+  }
   if (H.prof) {
     e2 = prof_event(H);
     H2_HIP(hipEventRecord(e2, st));
@@ -689,7 +806,8 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
 }  // namespace
 
 bool matvec_multi_supported(const h2_handle_s& H) {
-  if (H.host_only || H.otf || H.P.storage != H2_F32 || H.S.k != 64) return false;
+  if (H.host_only || H.P.storage != H2_F32 || H.S.k != 64) return false;
+  if (H.otf && H.is_complex) return false;
   for (int32_t c : H.S.leaves)
     if (H.S.cend[c] - H.S.cbegin[c] > 64) return false;  // one MFMA K-chunk per leaf
   return true;

@@ -112,16 +112,17 @@ def test_laplace_sampled_rows_327k_dense_x():
     assert err("f64", y[rows], val, None) <= 1e-12
 
 
-def test_multi_rhs_closed_form_cube786k():
+@pytest.mark.parametrize("otf", [False, True])
+def test_multi_rhs_closed_form_cube786k(otf):
     """The many-right-hand-side (matrix-core) path in the configuration the
-    many-RHS benchmark times: 786,432-triangle cube, 64 columns, FP32 storage;
-    every column against the (x.y)^2 closed form, in the FP32 norm of that
-    column, and the block reproducible."""
-    print("multi-RHS closed form cube786k", flush=True)
+    many-RHS benchmark times: 786,432-triangle cube, 64 columns, FP32 storage,
+    S stored or evaluated on the fly; every column against the (x.y)^2 closed
+    form, in the FP32 norm of that column, and the block reproducible."""
+    print("multi-RHS closed form cube786k otf=%s" % otf, flush=True)
     V, T = I.mesh_for("cube", 256)
     n, R = T.shape[0], 64
     X = I.random_vector(n, 4, "normal", nrhs=R)
-    A = h2.H2Matrix(V, T, kernel="quadratic", order=4, leaf=64, eta=0.5, storage="f32")
+    A = h2.H2Matrix(V, T, kernel="quadratic", order=4, leaf=64, eta=0.5, storage="f32", coupling_otf=otf)
     try:
         xd = torch.tensor(X, dtype=torch.float64, device="cuda").t().contiguous().t()
         yd = torch.zeros_like(xd)

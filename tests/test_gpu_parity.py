@@ -186,13 +186,15 @@ def test_closed_forms_medium(kernel, m, name, mesh):
 @pytest.mark.parametrize("case", [("sphere", 3, 4, 16), ("sphere", 3, 4, 64), ("cube", 16, 4, 32),
                                   ("sphere", 2, 4, 100)])
 @pytest.mark.parametrize("nrhs", [2, 17, 32, 33, 64, 70])
-def test_multi_rhs_matches_oracle(case, nrhs):
-    """Many right-hand sides (matrix-core path, FP32 storage, k = 64): every
-    column against the oracle, in the FP32 norm of each column."""
+@pytest.mark.parametrize("otf", [False, True])
+def test_multi_rhs_matches_oracle(case, nrhs, otf):
+    """Many right-hand sides (matrix-core path, FP32 storage, k = 64; S stored or
+    evaluated on the fly): every column against the oracle, in the FP32 norm of
+    each column."""
     kind, level, m, leaf = case
     H = oracle(kind, level, m, leaf)
     X = I.random_vector(H.mesh.n, 11, "normal", nrhs=nrhs)
-    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage="f32")
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage="f32", coupling_otf=otf)
     try:
         xd = torch.tensor(X, dtype=torch.float64, device="cuda").t().contiguous().t()
         Y0 = I.random_vector(H.mesh.n, 12, "normal", nrhs=nrhs)
