@@ -296,7 +296,8 @@ def bench_serve(args):
     meshes = {"sphere%d" % r: I.icosphere(r) for r in (4, 5, 6, 7)}
     meshes.update({"cube%d" % N: I.cube_surface(N) for N in (32, 64, 128)})
     kernels = [("laplace", 0.0), ("helmholtz", 2.0), ("helmholtz", 4.0)]
-    S = H2Server(GPUBackend(order=4, leaf=64, eta=0.5, storage="f32"), mem_budget=args.serve_budget_gb * 1e9,
+    S = H2Server(GPUBackend(order=4, leaf=64, eta=0.5, storage="f32", coupling_otf=not args.no_otf),
+                 mem_budget=args.serve_budget_gb * 1e9,
                  max_active=args.serve_slots)
     for name, (V, T) in meshes.items():
         S.register_mesh(name, V, T)
@@ -340,7 +341,8 @@ def bench_serve(args):
         "config": {"workload": "serve_mix", "meshes": {k: int(v[1].shape[0]) for k, v in meshes.items()},
                    "kernels": ["laplace", "helmholtz k=2", "helmholtz k=4"], "rhs": "U{1..16}",
                    "arrival_rate_per_s": args.serve_rate, "rtol": 1e-8, "slots": args.serve_slots,
-                   "storage": "f32 (FP64 iterative refinement)"},
+                   "storage": "f32 (FP64 iterative refinement)",
+                   "laplace_coupling": "stored" if args.no_otf else "evaluated during the product"},
         "serving": dict(st, build_s=build_s, span_s=span, resident_GB=S.used_bytes() / 1e9,
                         failures=S.failures()[:20],
                         iterations_mean=float(np.mean([q.iterations for q in S.finished])),

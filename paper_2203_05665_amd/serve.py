@@ -39,12 +39,17 @@ import numpy as np
 class GPUBackend:
     """Builds H^2 matrices with the HIP library; vectors are CUDA tensors."""
 
-    def __init__(self, order=4, leaf=64, eta=0.5, storage="f32", device="cuda"):
+    def __init__(self, order=4, leaf=64, eta=0.5, storage="f32", device="cuda", coupling_otf=False):
         import torch
         from . import h2
         self.torch, self.h2 = torch, h2
         self.order, self.leaf, self.eta, self.storage = order, leaf, eta, storage
         self.device = torch.device(device)
+        # real kernels may evaluate the coupling matrices during each product instead of storing them
+        self.coupling_otf = coupling_otf
+
+    def _otf(self, kernel):
+        return self.coupling_otf and kernel != "helmholtz" and self.storage in ("f32", "f64")
 
     def estimate(self, V, T, kernel, kappa):
         """Device bytes of the structure, from a host-only build of its trees."""
@@ -59,13 +64,14 @@ class GPUBackend:
         vb = 8 if self.storage == "f64" else 4
         sb = {"f64": 8, "f32": 4, "f32_sbf16": 2}[self.storage]
         k, n, nc = i["k"], i["n"], i["nclusters"]
-        data = cw * (sb * k * k * i["n_adm"] + vb * i["near_entries"]) + vb * (4 * n * k + 2 * k * k * nc)
+        s_bytes = 0 if self._otf(kernel) else sb * k * k * i["n_adm"]
+        data = cw * (s_bytes + vb * i["near_entries"]) + vb * (4 * n * k + 2 * k * k * nc + 48 * nc) + 8 * 15 * nc
         work = 2 * 8 * cw * (n + nc * k) + 4 * 64 * (2 * n + 2 * nc * k)   # one- and many-RHS workspaces
         return int(data + work)
 
     def build(self, V, T, kernel, kappa):
         A = self.h2.H2Matrix(V, T, kernel=kernel, kappa=kappa, order=self.order, leaf=self.leaf, eta=self.eta,
-                             storage=self.storage)
+                             storage=self.storage, coupling_otf=self._otf(kernel))
         return A, self.estimate(V, T, kernel, kappa)
 
     def matvec(self, A, X, Y, acc64, stream):

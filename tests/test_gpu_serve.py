@@ -23,8 +23,9 @@ from paper_2203_05665_amd.serve import GPUBackend, H2Server  # noqa: E402
 MESHES = {"s3": I.icosphere(3), "s4": I.icosphere(4), "c16": I.cube_surface(16)}
 
 
-def server(storage="f32"):
-    S = H2Server(GPUBackend(order=4, leaf=64, eta=0.5, storage=storage), mem_budget=60e9, max_active=16)
+def server(storage="f32", otf=False):
+    S = H2Server(GPUBackend(order=4, leaf=64, eta=0.5, storage=storage, coupling_otf=otf), mem_budget=60e9,
+                 max_active=16)
     for k, (V, T) in MESHES.items():
         S.register_mesh(k, V, T)
     return S
@@ -46,9 +47,11 @@ def workload():
     return reqs
 
 
-def test_mix_equals_alone_and_converges():
+@pytest.mark.parametrize("otf", [False, True])
+def test_mix_equals_alone_and_converges(otf):
+    """Laplace structures with stored or on-the-fly coupling matrices."""
     W = workload()
-    S = server()
+    S = server(otf=otf)
     t0 = S.clock()
     mixed = [S.submit(w["mesh"], w["b"], kernel=w["kernel"], kappa=w["kappa"], rtol=1e-8, arrival=t0 + w["arrival"])
              for w in W]
@@ -58,7 +61,7 @@ def test_mix_equals_alone_and_converges():
     assert st["done"] == len(W)
     assert st["batched_products"] < sum(q.products for q in mixed)   # products were shared
     for w, qm in zip(W, mixed):
-        A = server()
+        A = server(otf=otf)
         qa = A.submit(w["mesh"], w["b"], kernel=w["kernel"], kappa=w["kappa"], rtol=1e-8)
         A.run()
         assert qa.status == "done"
