@@ -85,6 +85,15 @@ extern "C" {
                              evaluates in FP64, FP32 storage in FP32 from FP64 cluster-centre
                              differences plus FP32 offsets. */
 
+#define H2_SYMMETRIC 4    /* store one block of every symmetric pair (G~ = G~^T because test and
+                             trial spaces coincide and g is symmetric): coupling blocks (tau,
+                             sigma) with sigma > tau and near-field blocks whose column leaf is
+                             not before the row leaf; each kept off-diagonal block is applied
+                             as itself and as its transpose.  Real kernels, FP64 or FP32
+                             storage, k = 64, leaves of at most 64 triangles; single right-hand
+                             side kernels (several columns are applied one at a time).  With
+                             H2_COUPLING_OTF only the near field is halved. */
+
 typedef struct h2_handle_s* h2_handle;
 
 typedef struct {
@@ -102,7 +111,7 @@ typedef struct {
   double eta;     /* admissibility parameter of eq. admissibility             */
   int q_ss;       /* Gauss-Legendre order per axis of the Sauter-Schwab rules */
   int storage;    /* H2_F64, H2_F32, H2_F32_SBF16                             */
-  int flags;      /* 0, or H2_HOST_ONLY and/or H2_COUPLING_OTF                */
+  int flags;      /* 0 or any of H2_HOST_ONLY, H2_COUPLING_OTF, H2_SYMMETRIC  */
 } h2_params;
 
 typedef struct {
@@ -112,6 +121,8 @@ typedef struct {
   double matvec_bytes; /* algorithmic HBM bytes of one single-vector product:
                           V twice, E twice, S once, near field once */
   double matvec_flops; /* 2 flops per stored scalar used (x4 for complex)    */
+  int64_t s_blocks_stored;     /* coupling blocks held in memory (0 on the fly)  */
+  int64_t near_entries_stored; /* near-field entries held in memory              */
 } h2_stats;
 
 /* Builds the H^2 matrix of the mesh (trees on the host, all matrix entries on

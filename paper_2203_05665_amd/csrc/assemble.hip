@@ -400,7 +400,7 @@ void assemble_typed(h2_handle_s& H) {
   H.F.alloc(nc * kk * sizeof(VT));
   H.ET.alloc(nc * kk * sizeof(VT));
   H.Smat.alloc(H.otf ? 16 : static_cast<int64_t>(S.adm_col.size()) * kk * cw * sizeof(SST));
-  H.Nmat.alloc(S.near_entries * cw * sizeof(VT));
+  H.Nmat.alloc(S.near_stored * cw * sizeof(VT));
   H2_HIP(hipMemset(H.F.p, 0, H.F.bytes));
   H2_HIP(hipMemset(H.ET.p, 0, H.ET.bytes));
 
@@ -496,6 +496,8 @@ void assemble_typed(h2_handle_s& H) {
       const int64_t r = S.cend[tau] - S.cbegin[tau];
       for (int32_t t2 : nb) {
         const int32_t q = inv[t2];
+        // symmetric storage keeps the pair in the block of the earlier leaf only
+        if (S.sym_n && S.leaf_of_pos[q] < l) continue;
         const int32_t sc = S.leaves[S.leaf_of_pos[q]];
         // the near block (l, sc): columns of row l are sorted by cluster start
         const int64_t lo = S.near_ptr[l], hi = S.near_ptr[l + 1];

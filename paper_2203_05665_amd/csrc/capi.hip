@@ -106,8 +106,17 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
       H->otf = (P.flags & H2_COUPLING_OTF) != 0;
       if (H->otf && (H->is_complex || P.storage == H2_F32_SBF16))
         throw h2::Error(H2_EINVAL, "on-the-fly coupling needs a real kernel and FP64 or FP32 storage");
+      const bool sym = (P.flags & H2_SYMMETRIC) != 0;
+      if (sym && (H->is_complex || P.storage == H2_F32_SBF16 || P.order_m != 4))
+        throw h2::Error(H2_EINVAL, "symmetric storage needs a real kernel, FP64 or FP32 storage and m = 4");
       h2::build_structure(H->S, mesh->vertices, mesh->nv, mesh->triangles, mesh->nt, P.order_m, P.leaf_size,
                           P.eta);
+      if (sym) {
+        for (int32_t c : H->S.leaves)
+          if (H->S.cend[c] - H->S.cbegin[c] > 64)
+            throw h2::Error(H2_EINVAL, "symmetric storage needs leaves of at most 64 triangles");
+        h2::make_symmetric(H->S, !H->otf, true);
+      }
       if (!H->host_only) {
         H2_HIP(hipGetDevice(&H->device));
         const h2::Structure& S = H->S;
@@ -133,6 +142,18 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
           H->up_ptr[l + 1] = static_cast<int64_t>(ul.size());
         }
         H->up_list.upload(ul);
+        if (S.sym_s) {
+          H->adm_in_ptr.upload(S.adm_in_ptr);
+          H->adm_in_blk.upload(S.adm_in_blk);
+          H->scr_s.alloc(S.adm_col.size() * 64 * 8);
+        }
+        if (S.sym_n) {
+          H->near_slot.upload(S.near_slot);
+          H->near_in_ptr.upload(S.near_in_ptr);
+          H->near_in_slot.upload(S.near_in_slot);
+          H->leaf_of_pos.upload(S.leaf_of_pos);
+          H->scr_n.alloc(static_cast<size_t>(S.near_scratch) * 8);
+        }
         const int cw = H->is_complex ? 2 : 1;
         H->xc.alloc(S.n * 8 * cw);
         H->yc.alloc(S.n * 8 * cw);
@@ -178,9 +199,11 @@ int h2_info(h2_handle h, h2_stats* out) {
     out->nclusters = S.nclusters;
     out->nleaves = static_cast<int64_t>(S.leaves.size());
     out->depth = S.depth;
-    out->n_adm = static_cast<int64_t>(S.adm_col.size());
-    out->n_near = static_cast<int64_t>(S.near_col.size());
+    out->n_adm = S.adm_blocks;
+    out->n_near = S.near_blocks;
     out->near_entries = S.near_entries;
+    out->s_blocks_stored = h->otf ? 0 : static_cast<int64_t>(S.adm_col.size());
+    out->near_entries_stored = S.near_stored;
     out->m = S.m;
     out->k = S.k;
     out->storage = h->P.storage;
@@ -197,7 +220,10 @@ int h2_info(h2_handle h, h2_stats* out) {
     // V twice; E twice, in Kronecker form (3 m^2 numbers per cluster) on the k = 64 path
     const double e_per = S.k == 64 ? 3.0 * S.m * S.m : k * k;
     const double v_e = 2.0 * S.n * k + 2.0 * e_per * (S.nclusters - 1);
-    out->matvec_bytes = vb * v_e + cw * ((h->otf ? 0.0 : sb * k * k * out->n_adm) + vb * static_cast<double>(S.near_entries));
+    // every stored entry of S and of the near field is read once (symmetric storage: each
+    // kept block serves both of its uses in the same pass)
+    out->matvec_bytes = vb * v_e + cw * (sb * k * k * static_cast<double>(out->s_blocks_stored) +
+                                         vb * static_cast<double>(S.near_stored));
     out->matvec_flops = 2.0 * (v_e * (h->is_complex ? 2.0 : 1.0) +
                                (h->is_complex ? 4.0 : 1.0) * (k * k * out->n_adm + static_cast<double>(S.near_entries)));
     return H2_OK;
@@ -249,6 +275,7 @@ int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap) {
         return H2_OK;
       }
       case H2_X_ADM: {
+        if (S.sym_s) return fail(H2_EINVAL, "admissible blocks are stored once per symmetric pair (H2_SYMMETRIC)");
         std::vector<int32_t> v;
         for (int c = 0; c < nc; ++c)
           for (int64_t b = S.adm_ptr[c]; b < S.adm_ptr[c + 1]; ++b) { v.push_back(c); v.push_back(S.adm_col[b]); }
@@ -256,6 +283,7 @@ int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap) {
         return H2_OK;
       }
       case H2_X_NEAR: {
+        if (S.sym_n) return fail(H2_EINVAL, "near-field blocks are stored once per symmetric pair (H2_SYMMETRIC)");
         std::vector<int32_t> v;
         for (size_t l = 0; l < S.leaves.size(); ++l)
           for (int64_t b = S.near_ptr[l]; b < S.near_ptr[l + 1]; ++b) { v.push_back(S.leaves[l]); v.push_back(S.near_col[b]); }
@@ -279,6 +307,8 @@ int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap) {
     };
     std::vector<double> v;
     if (what == H2_X_S && h->otf) return fail(H2_EINVAL, "coupling matrices are not stored (H2_COUPLING_OTF)");
+    if ((what == H2_X_S || what == H2_X_N) && (S.sym_s || S.sym_n))
+      return fail(H2_EINVAL, "blocks are stored once per symmetric pair (H2_SYMMETRIC)");
     if (what == H2_X_V) {
       if (index < 0 || index >= nc || S.child0[index] >= 0) return fail(H2_EINVAL, "not a leaf cluster");
       const int64_t b0 = S.cbegin[index], r = S.cend[index] - b0;

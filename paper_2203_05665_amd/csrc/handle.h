@@ -81,6 +81,9 @@ struct h2_handle_s {
   // E_c = E_x (x) E_y (x) E_z: per cluster the three m x m one-dimensional factors,
   // E1[c][d][i][j] = l_j(xi_i) along axis d (i child point, j parent polynomial)
   h2::DBuf E1;
+  // symmetric storage: incoming lists, near-field scratch slots, and the scratch
+  // of the transposed products (sized for FP64 accumulation)
+  h2::DBuf adm_in_ptr, adm_in_blk, near_slot, near_in_ptr, near_in_slot, leaf_of_pos, scr_s, scr_n;
   // workspaces (sized for FP64 vectors, one right-hand side)
   h2::DBuf xc, yc, xhat, yhat;
   // many-right-hand-side workspaces (FP32, grown on first use)

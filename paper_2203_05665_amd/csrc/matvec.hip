@@ -312,6 +312,101 @@ __global__ __launch_bounds__(256) void coupling64(int nc, const int64_t* __restr
   }
 }
 
+// Symmetric storage (G~ = G~^T, so S_{sigma tau} = S_{tau sigma}^T): only the
+// blocks (tau, sigma) with sigma > tau are kept, and each one is used twice:
+// y^_tau += S x^_sigma (row sums) and S^T x^_tau (column sums), the latter into
+// the block's scratch slot, which adm_gather adds to y^_sigma afterwards in a
+// fixed order.  One workgroup per row cluster; wave w takes the kept blocks
+// w, w + 4, ... of the row and reads each with 16-byte loads: a lane owns VEC
+// consecutive columns of NR rows, so its row sums carry across the wave's
+// blocks and a block's column sums need one reduction over RPI lanes.
+template <typename SST, typename AT>
+__global__ __launch_bounds__(256) void coupling64_sym(int nc, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col, const SST* __restrict__ S,
+                                                      const AT* __restrict__ xhat, AT* __restrict__ yhat,
+                                                      AT* __restrict__ scratch) {
+  constexpr int VEC = Vec16<SST>::N;  // columns per lane
+  constexpr int LPR = 64 / VEC;       // lanes per block row
+  constexpr int RPI = 64 / LPR;       // rows per load instruction
+  constexpr int NR = 64 / RPI;        // rows per lane
+  constexpr int CH = NR < 8 ? NR : 8; // loads in flight
+  __shared__ AT part[3][64];
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int lane = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int lr = lane % LPR, r0 = lane / LPR;
+  AT xt[NR], acc[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    xt[j] = xhat[static_cast<int64_t>(tau) * 64 + r0 + RPI * j];
+    acc[j] = 0;
+  }
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau] + w; b < b1; b += 4) {
+    const int64_t s = col[b];
+    AT xs[VEC], cp[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      xs[v] = xhat[s * 64 + lr * VEC + v];
+      cp[v] = 0;
+    }
+    const SST* Sb = S + b * 4096 + lr * VEC;
+#pragma unroll
+    for (int j0 = 0; j0 < NR; j0 += CH) {
+      AT sv[CH][VEC];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) Vec16<SST>::load(Sb + (r0 + RPI * (j0 + u)) * 64, sv[u]);
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          acc[j0 + u] += sv[u][v] * xs[v];
+          cp[v] += sv[u][v] * xt[j0 + u];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+#pragma unroll
+      for (int off = LPR; off < 64; off <<= 1) cp[v] += __shfl_xor(cp[v], off);
+    if (r0 == 0) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) scratch[b * 64 + lr * VEC + v] = cp[v];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+  if (w > 0 && lr == 0) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) part[w - 1][r0 + RPI * j] = acc[j];
+  }
+  __syncthreads();
+  if (w == 0 && lr == 0) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const int row = r0 + RPI * j;
+      yhat[static_cast<int64_t>(tau) * 64 + row] = ((acc[j] + part[0][row]) + part[1][row]) + part[2][row];
+    }
+  }
+}
+
+// y^_c += the transposed parts of the kept blocks (tau, c), in increasing tau
+template <typename AT>
+__global__ __launch_bounds__(256) void adm_gather(int nc, const int64_t* __restrict__ in_ptr,
+                                                  const int64_t* __restrict__ in_blk, const AT* __restrict__ scratch,
+                                                  AT* __restrict__ yhat) {
+  const int c = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (c >= nc) return;
+  const int64_t i0 = in_ptr[c], i1 = in_ptr[c + 1];
+  if (i0 == i1) return;
+  AT s = 0;
+  for (int64_t i = i0; i < i1; ++i) s += scratch[in_blk[i] * 64 + lane];
+  yhat[static_cast<int64_t>(c) * 64 + lane] += s;
+}
+
 // any k: one thread per row nu of the block row
 template <typename SST, typename AT>
 __device__ inline AT lds(const SST* p);
@@ -545,6 +640,126 @@ __global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const i
     if (wave == 0 && i < r) yc[b0 + i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------- symmetric near field
+// Sum over lanes of p[j], delivered to lane j: 64 values per lane (32 for FP64,
+// where the two lane halves are added first and lane j & 31 receives column j),
+// by recursive halving: at each step a lane keeps the half of its values
+// selected by its lane bit, summed with the partner's copy of that half.  Both
+// halves are exchanged and the choice is made between the two sums, never
+// between array elements, so the array stays in registers.
+template <typename AT, int NV>
+__device__ inline AT transpose_reduce(AT (&p)[NV]) {
+  const int lane = threadIdx.x % 64;
+  if (NV == 32) {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) p[q] += __shfl_xor(p[q], 32);
+  }
+#pragma unroll
+  for (int s = NV / 2; s >= 1; s >>= 1) {
+    const bool up = (lane & s) != 0;
+#pragma unroll
+    for (int q = 0; q < s; ++q) {
+      const AT lo = p[q] + __shfl_xor(p[q], s);
+      const AT hi = p[q + s] + __shfl_xor(p[q + s], s);
+      p[q] = up ? hi : lo;
+    }
+  }
+  return p[0];
+}
+
+// Near field with symmetric storage (leaves of at most 64 triangles): the panel
+// of leaf tau holds its blocks (tau, sigma) with sigma not before tau.  One
+// workgroup per leaf, blocks dealt to the four waves, lane = row.  An
+// off-diagonal block also yields G^T x|tau (column sums over the lanes), written
+// to the block's scratch slot; permute_out_sym adds the slots of each leaf.
+template <typename ST, typename AT>
+__global__ __launch_bounds__(256) void near_backward_sym(int nleaves, const int32_t* __restrict__ leaves,
+                                                         const int32_t* __restrict__ cbegin,
+                                                         const int32_t* __restrict__ cend,
+                                                         const int64_t* __restrict__ near_ptr,
+                                                         const int32_t* __restrict__ near_col,
+                                                         const int64_t* __restrict__ panel_off,
+                                                         const int64_t* __restrict__ near_slot,
+                                                         const ST* __restrict__ N, const ST* __restrict__ Vb,
+                                                         const AT* __restrict__ xc, const AT* __restrict__ yhat,
+                                                         AT* __restrict__ yc, AT* __restrict__ scratch) {
+  constexpr int NV = sizeof(AT) == 4 ? 64 : 32;  // columns per transposed reduction
+  __shared__ AT part[4][64];
+  const int l = blockIdx.x;
+  if (l >= nleaves) return;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int32_t tau = leaves[l];
+  const int64_t b0 = cbegin[tau];
+  const int r = cend[tau] - cbegin[tau];
+  const int is = lane < r ? lane : r - 1;
+  const AT xt = lane < r ? xc[b0 + lane] : AT(0);
+  const ST* P = N + panel_off[l];
+  AT acc = 0;
+  int64_t colbase = 0;
+  const int64_t bfirst = near_ptr[l], blast = near_ptr[l + 1];
+  for (int64_t bb = bfirst; bb < blast; ++bb) {
+    const int32_t s = near_col[bb];
+    const int64_t s0 = cbegin[s];
+    const int w = cend[s] - cbegin[s];
+    if (((bb - bfirst) & 3) == wave) {
+      const AT xv = lane < w ? xc[s0 + lane] : AT(0);
+      const ST* A = P + colbase * r + is;
+      const int64_t slot = near_slot[bb];
+      if (slot < 0) {
+        acc = stream_dot<ST, AT>(A, r, w, xv, acc);
+      } else {
+        // straight-line over all column slots of the chunk, loads clamped to the
+        // last column: beyond w the row products vanish (xv is 0 there) and the
+        // column partials are computed but never stored
+#pragma unroll
+        for (int c0 = 0; c0 < 64; c0 += NV) {
+          if (c0 < w) {
+            AT p[NV];
+#pragma unroll
+            for (int j = 0; j < NV; j += 8) {
+              AT a[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) a[u] = ld<ST, AT>(A + min(c0 + j + u, w - 1) * r);
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                acc += a[u] * bcast(xv, c0 + j + u);
+                p[j + u] = a[u] * xt;
+              }
+            }
+            const AT t = transpose_reduce<AT, NV>(p);
+            if (lane < NV && c0 + lane < w) scratch[slot + c0 + lane] = t;
+          }
+        }
+      }
+    }
+    colbase += w;
+  }
+  // leaf backward: columns nu of V_tau, a quarter per wave
+  const ST* Vl = Vb + b0 * 64;
+  const AT yv = lane < 16 ? yhat[static_cast<int64_t>(tau) * 64 + 16 * wave + lane] : AT(0);
+  acc = stream_dot<ST, AT>(Vl + static_cast<int64_t>(16 * wave) * r + is, r, 16, yv, acc);
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && lane < r) yc[b0 + lane] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// y[perm[p]] += alpha (y_c[p] + the transposed near-field parts addressed to p's leaf)
+template <typename XT, typename AT>
+__global__ void permute_out_sym(int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ leaf_of_pos,
+                                const int32_t* __restrict__ leaves, const int32_t* __restrict__ cbegin,
+                                const int64_t* __restrict__ in_ptr, const int64_t* __restrict__ in_slot,
+                                const AT* __restrict__ scratch, const AT* __restrict__ yc, XT* __restrict__ y,
+                                double alpha) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t l = leaf_of_pos[p];
+  const int64_t off = p - cbegin[leaves[l]];
+  AT v = yc[p];
+  for (int64_t i = in_ptr[l]; i < in_ptr[l + 1]; ++i) v += scratch[in_slot[i] + off];
+  const int64_t t = perm[p];
+  y[t] = static_cast<XT>(static_cast<double>(y[t]) + alpha * static_cast<double>(v));
 }
 
 // ---------------------------------------------------------------- complex kernels (Helmholtz)
@@ -797,6 +1012,11 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
   if (H.otf) {
     if (H.P.storage == H2_F64) launch_otf<double, AT>(H, xh, yh, st);
     else launch_otf<float, AT>(H, xh, yh, st);
+  } else if (S.sym_s) {
+    coupling64_sym<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
+                                               H.Smat.as<SST>(), xh, yh, H.scr_s.as<AT>());
+    adm_gather<AT><<<blocks_for(nc, 4), 256, 0, st>>>(nc, H.adm_in_ptr.as<int64_t>(), H.adm_in_blk.as<int64_t>(),
+                                                      H.scr_s.as<AT>(), yh);
   } else if (k == 64) {
     coupling64<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<SST>(),
                                            xh, yh);
@@ -813,11 +1033,22 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
     e3 = prof_event(H);
     H2_HIP(hipEventRecord(e3, st));
   }
-  near_backward<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
-                                            H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
-                                            H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
-                                            H.Vb.as<ST>(), xc, yh, yc);
-  permute_out<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), yc, y, alpha);
+  if (S.sym_n) {
+    near_backward_sym<ST, AT><<<nl, 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                  H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                                  H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
+                                                  H.near_slot.as<int64_t>(), H.Nmat.as<ST>(), H.Vb.as<ST>(), xc, yh,
+                                                  yc, H.scr_n.as<AT>());
+    permute_out_sym<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(
+        n, H.perm.as<int32_t>(), H.leaf_of_pos.as<int32_t>(), H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+        H.near_in_ptr.as<int64_t>(), H.near_in_slot.as<int64_t>(), H.scr_n.as<AT>(), yc, y, alpha);
+  } else {
+    near_backward<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                              H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                              H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
+                                              H.Vb.as<ST>(), xc, yh, yc);
+    permute_out<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), yc, y, alpha);
+  }
   H2_HIP(hipGetLastError());
   if (H.prof) {
     e4 = prof_event(H);

@@ -872,6 +872,7 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
 bool matvec_multi_supported(const h2_handle_s& H) {
   if (H.host_only || H.P.storage != H2_F32 || H.S.k != 64) return false;
   if (H.otf && H.is_complex) return false;
+  if (H.S.sym_s || H.S.sym_n) return false;  // kept blocks are applied by the single-vector kernels
   for (int32_t c : H.S.leaves)
     if (H.S.cend[c] - H.S.cbegin[c] > 64) return false;  // one MFMA K-chunk per leaf
   return true;

@@ -240,6 +240,75 @@ void build_structure(Structure& S, const double* vertices, int64_t nv, const int
     S.panel_off[l + 1] = S.panel_off[l] + r * cols;
   }
   S.near_entries = S.panel_off[nl];
+  S.near_stored = S.near_entries;
+  S.adm_blocks = static_cast<int64_t>(S.adm_col.size());
+  S.near_blocks = static_cast<int64_t>(S.near_col.size());
+}
+
+void make_symmetric(Structure& S, bool s, bool nf) {
+  const int32_t nc = S.nclusters;
+  const int32_t nl = static_cast<int32_t>(S.leaves.size());
+  if (s) {
+    std::vector<int64_t> ptr(nc + 1, 0);
+    std::vector<int32_t> col;
+    for (int32_t t = 0; t < nc; ++t) {
+      for (int64_t b = S.adm_ptr[t]; b < S.adm_ptr[t + 1]; ++b)
+        if (S.adm_col[b] > t) col.push_back(S.adm_col[b]);
+      ptr[t + 1] = static_cast<int64_t>(col.size());
+    }
+    S.adm_ptr.swap(ptr);
+    S.adm_col.swap(col);
+    // incoming: block b = (t, sigma) contributes S_b^T x^_t to sigma; gathered by increasing t
+    S.adm_in_ptr.assign(nc + 1, 0);
+    for (int32_t c : S.adm_col) S.adm_in_ptr[c + 1]++;
+    for (int32_t c = 0; c < nc; ++c) S.adm_in_ptr[c + 1] += S.adm_in_ptr[c];
+    S.adm_in_blk.resize(S.adm_col.size());
+    std::vector<int64_t> fill(S.adm_in_ptr.begin(), S.adm_in_ptr.end() - 1);
+    for (int32_t t = 0; t < nc; ++t)
+      for (int64_t b = S.adm_ptr[t]; b < S.adm_ptr[t + 1]; ++b) S.adm_in_blk[fill[S.adm_col[b]]++] = b;
+    S.sym_s = true;
+  }
+  if (nf) {
+    std::vector<int32_t> leaf_index(nc, -1);
+    for (int32_t l = 0; l < nl; ++l) leaf_index[S.leaves[l]] = l;
+    std::vector<int64_t> ptr(nl + 1, 0);
+    std::vector<int32_t> col;
+    for (int32_t l = 0; l < nl; ++l) {
+      for (int64_t b = S.near_ptr[l]; b < S.near_ptr[l + 1]; ++b)
+        if (leaf_index[S.near_col[b]] >= l) col.push_back(S.near_col[b]);
+      ptr[l + 1] = static_cast<int64_t>(col.size());
+    }
+    S.near_ptr.swap(ptr);
+    S.near_col.swap(col);
+    S.panel_off.assign(nl + 1, 0);
+    S.near_slot.assign(S.near_col.size(), -1);
+    S.near_in_ptr.assign(nl + 1, 0);
+    int64_t slot = 0;
+    for (int32_t l = 0; l < nl; ++l) {
+      const int64_t r = S.cend[S.leaves[l]] - S.cbegin[S.leaves[l]];
+      int64_t cols = 0;
+      for (int64_t b = S.near_ptr[l]; b < S.near_ptr[l + 1]; ++b) {
+        const int32_t c = S.near_col[b];
+        const int64_t w = S.cend[c] - S.cbegin[c];
+        cols += w;
+        if (leaf_index[c] != l) {
+          S.near_slot[b] = slot;
+          slot += w;
+          S.near_in_ptr[leaf_index[c] + 1]++;
+        }
+      }
+      S.panel_off[l + 1] = S.panel_off[l] + r * cols;
+    }
+    for (int32_t l = 0; l < nl; ++l) S.near_in_ptr[l + 1] += S.near_in_ptr[l];
+    S.near_in_slot.resize(S.near_in_ptr[nl]);
+    std::vector<int64_t> fill(S.near_in_ptr.begin(), S.near_in_ptr.end() - 1);
+    for (int32_t l = 0; l < nl; ++l)
+      for (int64_t b = S.near_ptr[l]; b < S.near_ptr[l + 1]; ++b)
+        if (S.near_slot[b] >= 0) S.near_in_slot[fill[leaf_index[S.near_col[b]]]++] = S.near_slot[b];
+    S.near_scratch = slot;
+    S.near_stored = S.panel_off[nl];
+    S.sym_n = true;
+  }
 }
 
 }  // namespace h2

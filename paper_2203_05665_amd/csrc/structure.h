@@ -40,7 +40,25 @@ struct Structure {
   std::vector<int32_t> near_col;
   std::vector<int64_t> panel_off;    // per leaf: element offset of its near-field panel
   int64_t near_entries = 0;          // sum over inadmissible leaves of |tau| |sigma|
+  int64_t near_stored = 0;           // entries held in the panels (= near_entries unless symmetric)
+  int64_t adm_blocks = 0;            // admissible leaves of the block tree (before any halving)
+  int64_t near_blocks = 0;           // inadmissible leaves of the block tree (before any halving)
+  // symmetric storage (G~ = G~^T): only blocks (tau, sigma) with sigma after tau are kept;
+  // each kept off-diagonal block also feeds the transposed product into a scratch slot,
+  // and every target gathers its incoming slots in a fixed order.
+  bool sym_s = false, sym_n = false;
+  std::vector<int64_t> adm_in_ptr;   // per cluster sigma: incoming blocks (tau, sigma), tau < sigma
+  std::vector<int64_t> adm_in_blk;   // their block indices (scratch slot = block index * k)
+  std::vector<int64_t> near_slot;    // per kept near block: scratch offset of its transposed part (-1: diagonal)
+  std::vector<int64_t> near_in_ptr;  // per leaf: incoming off-diagonal near blocks
+  std::vector<int64_t> near_in_slot; // their scratch offsets, by source leaf
+  int64_t near_scratch = 0;          // scratch values of the transposed near-field parts
 };
+
+// Keeps one block of every symmetric pair: admissible blocks (tau, sigma) with
+// sigma > tau (cluster ids) when `s`, inadmissible leaves with leaf index of
+// sigma >= that of tau when `nf`; builds the scratch slots and incoming lists.
+void make_symmetric(Structure& S, bool s, bool nf);
 
 // Builds tree and block tree.  Throws std::runtime_error on invalid input.
 void build_structure(Structure& S, const double* vertices, int64_t nv, const int32_t* triangles,

@@ -22,7 +22,7 @@ H2_LAPLACE, H2_HELMHOLTZ, H2_TEST_ONE, H2_TEST_BILINEAR, H2_TEST_QUADRATIC = 0, 
 H2_F64, H2_F32, H2_F32_SBF16 = 0, 1, 2
 H2_R64, H2_R32, H2_C128, H2_C64 = 0, 1, 2, 3
 H2_ACC_F64 = 1
-H2_HOST_ONLY, H2_COUPLING_OTF = 1, 2
+H2_HOST_ONLY, H2_COUPLING_OTF, H2_SYMMETRIC = 1, 2, 4
 H2_CG, H2_GMRES = 0, 1
 (H2_X_PERM, H2_X_CLUSTERS, H2_X_BOXES, H2_X_ADM, H2_X_NEAR, H2_X_DFS, H2_X_V, H2_X_E, H2_X_S,
  H2_X_N) = range(10)
@@ -47,7 +47,8 @@ class h2_stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in ("n", "nclusters", "nleaves", "depth", "n_adm", "n_near",
                                          "near_entries", "m", "k", "storage", "kernel", "bytes_S",
                                          "bytes_N", "bytes_V", "bytes_E", "bytes_total")] + \
-               [("matvec_bytes", C.c_double), ("matvec_flops", C.c_double)]
+               [("matvec_bytes", C.c_double), ("matvec_flops", C.c_double),
+                ("s_blocks_stored", C.c_int64), ("near_entries_stored", C.c_int64)]
 
 
 class h2_solve_params(C.Structure):
@@ -112,7 +113,7 @@ def h2_last_error() -> str:
 
 
 def build_h2(vertices, triangles, kernel="laplace", kappa=0.0, order=4, leaf=64, eta=0.5, q_ss=4,
-             storage="f64", host_only=False, coupling_otf=False):
+             storage="f64", host_only=False, coupling_otf=False, symmetric=False):
     """Calls build_h2; returns the raw handle (int)."""
     V = np.ascontiguousarray(vertices, dtype=np.float64)
     T = np.ascontiguousarray(triangles, dtype=np.int32)
@@ -120,7 +121,8 @@ def build_h2(vertices, triangles, kernel="laplace", kappa=0.0, order=4, leaf=64,
                    T.ctypes.data_as(C.POINTER(C.c_int32)))
     prm = h2_params(KERNELS[kernel] if isinstance(kernel, str) else int(kernel), float(kappa), int(order),
                     int(leaf), float(eta), int(q_ss), STORAGE[storage] if isinstance(storage, str) else int(storage),
-                    (H2_HOST_ONLY if host_only else 0) | (H2_COUPLING_OTF if coupling_otf else 0))
+                    (H2_HOST_ONLY if host_only else 0) | (H2_COUPLING_OTF if coupling_otf else 0) |
+                    (H2_SYMMETRIC if symmetric else 0))
     h = C.c_void_p()
     _check(lib().build_h2(C.byref(mesh), C.byref(prm), C.byref(h)))
     return h.value

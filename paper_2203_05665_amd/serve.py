@@ -296,6 +296,7 @@ class Request:
     _z: object = None
     _resid: object = None
     _outer_R: object = None
+    _bad_product: object = None    # device flag: some product returned a non-finite entry
 
     @property
     def key(self):
@@ -492,6 +493,8 @@ class H2Server:
 
     def _advance(self, q, Y):
         q.products += 1
+        bad = ~self.t.isfinite(self.t.view_as_real(Y) if Y.is_complex() else Y).all()
+        q._bad_product = bad if q._bad_product is None else (q._bad_product | bad)
         if q._phase == "outer":
             R = q.b - Y
             nb = self.t.linalg.vector_norm(q.b, dim=1)
@@ -511,7 +514,7 @@ class H2Server:
             if q._phase == "outer":
                 rel = float(q._resid.max())
                 if not math.isfinite(rel):
-                    q.status, q.error, finished = "failed", "non-finite residual", True
+                    q.status, q.error, finished = "failed", self._nonfinite(q, "outer residual"), True
                 elif rel <= q.rtol:
                     q.status, finished = "done", True
                     q.rel_residual = rel
@@ -536,7 +539,7 @@ class H2Server:
                     exhausted = s.it >= s.maxit
                 relmax = float(s.relres().max())
                 if not math.isfinite(relmax):
-                    q.status, q.error, finished = "failed", "non-finite residual", True
+                    q.status, q.error, finished = "failed", self._nonfinite(q, "inner residual"), True
                 elif converged:
                     if self._refine(q):
                         q._z = q._z + s.solution()
@@ -561,6 +564,16 @@ class H2Server:
             else:
                 keep.append(q)
         self.active = keep
+
+    def _nonfinite(self, q, where):
+        """Failure message: which residual, and whether a product itself returned a
+        non-finite entry (the library) or only the solver's arithmetic did."""
+        from_product = q._bad_product is not None and bool(q._bad_product)
+        detail = "a product returned a non-finite entry" if from_product else "all products were finite"
+        s = q._solver
+        if isinstance(s, _GMRES):
+            detail += "; GMRES step %d of cycle, phase %s" % (s.j, s.phase)
+        return "non-finite residual (%s after %d iterations; %s)" % (where, q.iterations, detail)
 
     def run(self, until_idle=True, max_ticks=10 ** 9, progress: Optional[Callable[[dict], None]] = None,
             progress_every: float = 5.0, deadline: Optional[float] = None):
@@ -614,10 +627,12 @@ class H2Server:
         }
 
     def failures(self) -> List[dict]:
-        """What each failed request was and why (mesh, kernel, width, iterations)."""
-        return [{"rid": q.rid, "mesh": q.mesh, "kernel": q.kernel, "kappa": q.kappa, "rhs": int(q.b.shape[0]),
-                 "iterations": q.iterations, "products": q.products, "error": q.error}
-                for q in self.finished if q.status == "failed"]
+        """What each failed or unconverged request was and why (mesh, kernel, width,
+        iterations, last relative residual)."""
+        return [{"rid": q.rid, "status": q.status, "mesh": q.mesh, "kernel": q.kernel, "kappa": q.kappa,
+                 "rhs": int(q.b.shape[0]), "iterations": q.iterations, "products": q.products,
+                 "rel_residual": q.rel_residual, "error": q.error}
+                for q in self.finished if q.status in ("failed", "not_converged")]
 
 
 class _nullcontext:

@@ -43,16 +43,18 @@ def run(A, x):
 
 
 @pytest.mark.parametrize("mesh", [("sphere", 8), ("cube", 256)])
-@pytest.mark.parametrize("storage", ["f64", "f32", "f32_otf"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32_otf", "f32_sym"])
 def test_closed_form_full_size(mesh, storage):
     print("closed form", mesh, storage, flush=True)
     V, T = I.mesh_for(*mesh)
     x = I.random_vector(T.shape[0], 3, "normal")
     ref = poly_kernel_product(V, T, "quadratic", x)
     ref_abs = poly_kernel_product(V, T, "quadratic", np.abs(x))   # g >= 0: |G| |x| = G |x|
-    otf = storage.endswith("_otf")
-    storage = storage.replace("_otf", "")
-    A = h2.H2Matrix(V, T, kernel="quadratic", order=4, leaf=64, eta=0.5, storage=storage, coupling_otf=otf)
+    otf = "_otf" in storage
+    sym = storage.endswith("_sym")
+    storage = storage.split("_")[0]
+    A = h2.H2Matrix(V, T, kernel="quadratic", order=4, leaf=64, eta=0.5, storage=storage, coupling_otf=otf,
+                    symmetric=sym)
     try:
         assert A.info["n_adm"] > 10 ** 5
         assert err(storage, run(A, x), ref, ref_abs) <= TOL[storage]
@@ -68,11 +70,12 @@ def oracle_tree(kind, level):
     return H2Oracle(V, T, Kernel(), m=4, leaf=64, eta=0.5, build_blocks=False)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f64_otf", "f32_otf"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f64_otf", "f32_otf", "f32_sym", "f32_otf_sym"])
 def test_laplace_sampled_rows_1310k(storage):
     print("laplace sampled rows 1310k", storage, flush=True)
-    otf = storage.endswith("_otf")
-    storage = storage.replace("_otf", "")
+    otf = "_otf" in storage
+    sym = storage.endswith("_sym")
+    storage = storage.split("_")[0]
     H = oracle_tree("sphere", 8)
     rng = np.random.default_rng(17)
     leaves = H.tree.leaves
@@ -84,7 +87,8 @@ def test_laplace_sampled_rows_1310k(storage):
     sample = [leaves[i].id for i in rng.choice(len(leaves), 10, replace=False)] + support[:4]
     ref = H.sampled_rows(x, sample, support=support)
     ref_abs = H.sampled_rows(np.abs(x), sample, support=support)
-    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=4, leaf=64, eta=0.5, storage=storage, coupling_otf=otf)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=4, leaf=64, eta=0.5, storage=storage, coupling_otf=otf,
+                    symmetric=sym)
     try:
         y = run(A, x)
     finally:

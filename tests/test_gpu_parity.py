@@ -248,3 +248,60 @@ def test_on_the_fly_closed_forms(kernel, m, name):
         assert rel(gpu_matvec(A, x), ref) <= 1e-12
     finally:
         A.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("otf", [False, True])
+@pytest.mark.parametrize("case", [("sphere", 3, 4, 16), ("sphere", 3, 4, 64), ("cube", 16, 4, 32),
+                                  ("sphere", 4, 4, 48)])
+def test_symmetric_storage_matches_oracle(case, storage, otf):
+    """One block per symmetric pair, applied as itself and as its transpose
+    (stored or on-the-fly S): the same product as the oracle, to the storage
+    precision's tolerance, with y accumulated (alpha) and with FP64 accumulation
+    over FP32 entries; bitwise reproducible; several columns apply one by one."""
+    kind, level, m, leaf = case
+    H = oracle(kind, level, m, leaf)
+    x = I.random_vector(H.mesh.n, 21, "normal")
+    y0 = I.random_vector(H.mesh.n, 22, "normal")
+    ref, ref_abs = H.matvec(x), H.matvec(np.abs(x))
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage=storage, coupling_otf=otf,
+                    symmetric=True)
+    try:
+        assert A.info["s_blocks_stored"] == (0 if otf else A.info["n_adm"] // 2)
+        y = gpu_matvec(A, x)
+        assert err(storage, y, ref, ref_abs) <= TOL[storage]
+        assert np.array_equal(gpu_matvec(A, x), y)
+        ya = gpu_matvec(A, x, y0=y0, alpha=-0.5)
+        # y0 ~ N(0,1) is much larger than G~x: its own FP64 rounding enters the bound
+        scale = np.linalg.norm(ref if storage == "f64" else ref_abs)
+        assert np.linalg.norm(ya - (y0 - 0.5 * ref)) <= 0.5 * TOL[storage] * scale + 4e-16 * np.linalg.norm(y0)
+        if storage == "f32":
+            assert err(storage, gpu_matvec(A, x, acc64=True), ref, ref_abs) <= TOL[storage]
+        X = np.asfortranarray(np.stack([x, y0], axis=1))
+        xd = torch.tensor(X, device="cuda").t().contiguous().t()
+        yd = torch.zeros_like(xd)
+        A.matvec(xd, yd)
+        Y = yd.cpu().numpy()
+        assert np.array_equal(Y[:, 0], y)
+        assert err(storage, Y[:, 1], H.matvec(y0), H.matvec(np.abs(y0))) <= TOL[storage]
+    finally:
+        A.close()
+
+
+def test_symmetric_storage_solve():
+    """CG through h2_solve on symmetric storage reaches the same solution as on
+    full storage (unit sphere, b_i = |T_i|, z ~ 1)."""
+    V, T = I.icosphere(4)
+    P = V[T]
+    b = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+    bd = torch.tensor(b, device="cuda")
+    out = {}
+    for sym in (False, True):
+        A = h2.H2Matrix(V, T, order=4, leaf=64, eta=0.5, storage="f64", symmetric=sym)
+        try:
+            z, info = A.solve(bd, method="cg", rtol=1e-10, maxit=500)
+            assert info["converged"]
+            out[sym] = z.cpu().numpy()
+        finally:
+            A.close()
+    assert np.linalg.norm(out[True] - out[False]) <= 1e-8 * np.linalg.norm(out[False])

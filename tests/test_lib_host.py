@@ -93,3 +93,40 @@ def test_structure_counts_at_full_size():
         assert info["n_adm"] > 0 and info["near_entries"] > 0
     finally:
         h2.h2_free(hdl)
+
+
+@pytest.mark.parametrize("mesh,otf", [(("sphere", 4), False), (("cube", 16), False), (("sphere", 5), True)])
+def test_symmetric_storage_keeps_one_block_per_pair(mesh, otf):
+    """H2_SYMMETRIC: the admissible set is symmetric and has no diagonal blocks,
+    so exactly half of its blocks are kept; the inadmissible set is symmetric and
+    contains every diagonal block (tau, tau), so the kept near-field entries are
+    half of the off-diagonal entries plus all diagonal ones.  Counted from the
+    oracle-checked full structure of the same mesh."""
+    V, T = I.mesh_for(*mesh)
+    full = h2.build_h2(V, T, order=4, leaf=64, eta=0.5, host_only=True)
+    sym = h2.build_h2(V, T, order=4, leaf=64, eta=0.5, host_only=True, symmetric=True, coupling_otf=otf)
+    try:
+        fi, si = h2.h2_info(full), h2.h2_info(sym)
+        assert si["n_adm"] == fi["n_adm"] and si["n_near"] == fi["n_near"]   # block tree unchanged
+        assert si["near_entries"] == fi["near_entries"]
+        assert fi["s_blocks_stored"] == fi["n_adm"] and fi["near_entries_stored"] == fi["near_entries"]
+        assert si["s_blocks_stored"] == (0 if otf else fi["n_adm"] // 2) and fi["n_adm"] % 2 == 0
+        cl = h2.h2_export(full, h2.H2_X_CLUSTERS).reshape(-1, 6)
+        leaves = cl[cl[:, 3] < 0]
+        diag = int(((leaves[:, 1] - leaves[:, 0]).astype(np.int64) ** 2).sum())
+        assert 2 * si["near_entries_stored"] - diag == fi["near_entries"]
+        assert si["matvec_bytes"] < fi["matvec_bytes"]
+        with pytest.raises(h2.H2Error):
+            h2.h2_export(sym, h2.H2_X_NEAR)
+    finally:
+        h2.h2_free(full)
+        h2.h2_free(sym)
+
+
+def test_symmetric_storage_rejects_unsupported_settings():
+    V, T = I.icosphere(3)
+    for kw in (dict(kernel="helmholtz", kappa=2.0), dict(order=3), dict(leaf=100), dict(storage="f32_sbf16")):
+        args = dict(order=4, leaf=64, eta=0.5, host_only=True, symmetric=True)
+        args.update(kw)
+        with pytest.raises(h2.H2Error):
+            h2.h2_free(h2.build_h2(V, T, **args))

@@ -223,6 +223,7 @@ def test_non_convergence_and_poisoned_products():
     p = P.submit("sphere1", np.ones(80), rtol=1e-8)
     P.run()
     assert p.status == "failed" and "non-finite" in p.error
+    assert "a product returned a non-finite entry" in p.error       # blamed on the product, not the solver
 
 
 def test_resident_structure_makes_room_for_request_vectors():
