@@ -211,6 +211,25 @@ def otf_roofline(info, coup_avg_ms, storage):
             "entries_per_launch": entries, "avg_launch_ms": coup_avg_ms}
 
 
+def variant_roofline(info, ph, storage, kw):
+    """Roofline of the dominant kernel of a variant: the on-the-fly coupling
+    (ALU) when it is the longest phase, else the phase that streams stored data
+    from HBM (symmetric coupling: the kept S blocks; near field: the kept panels
+    and V)."""
+    sb = {"f64": 8, "f32": 4}[storage]
+    if kw.get("coupling_otf") and ph["coupling"] >= ph["near"]:
+        return otf_roofline(info, ph["coupling"], storage)
+    if not kw.get("coupling_otf") and ph["coupling"] >= ph["near"]:
+        nbytes, kern = float(info["s_blocks_stored"]) * info["k"] ** 2 * sb, "coupling64_sym"
+        ms = ph["coupling"]
+    else:
+        nbytes = float(info["near_entries_stored"] + info["n"] * info["k"]) * sb
+        kern, ms = ("near_backward_sym" if kw.get("symmetric") else "near_backward"), ph["near"]
+    ach = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": kern, "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": ms}
+
+
 def _walk(c):
     yield c
     for ch in c.children:
@@ -443,18 +462,22 @@ def main():
     del A
     torch.cuda.empty_cache()
     if not otf and not args.no_otf and storage in ("f32", "f64"):
-        log("bench: variant with the coupling evaluated during the product")
-        B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage, coupling_otf=True)
-        yb = torch.zeros_like(x)
-        elb, profb = measure(B, x, yb, args.steps, args.warmup, torch, h2)
-        cb = profb["coupling"][0] / max(1, profb["coupling"][1])
-        out["otf_variant"] = {"value": args.steps / elb, "unit": "matvec/s", "ms_per_step": 1e3 * elb / args.steps,
-                              "device_bytes": B.info["bytes_total"],
-                              "phase_ms": {k: v[0] / max(1, v[1]) for k, v in profb.items()},
-                              "roofline": otf_roofline(B.info, cb, storage)}
-        B.close()
-        del B
-        torch.cuda.empty_cache()
+        # the same product from byte-reducing representations of the same G~
+        out["variants"] = {}
+        for vname, kw in (("coupling_on_the_fly", dict(coupling_otf=True)), ("symmetric", dict(symmetric=True)),
+                          ("coupling_on_the_fly+symmetric", dict(coupling_otf=True, symmetric=True))):
+            log("bench: variant %s" % vname)
+            B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage, **kw)
+            yb = torch.zeros_like(x)
+            elb, profb = measure(B, x, yb, args.steps, args.warmup, torch, h2)
+            ph = {k: v[0] / max(1, v[1]) for k, v in profb.items()}
+            out["variants"][vname] = {"value": args.steps / elb, "unit": "matvec/s", "ms_per_step": 1e3 * elb / args.steps,
+                                      "device_bytes": B.info["bytes_total"],
+                                      "algorithmic_bytes": B.info["matvec_bytes"], "phase_ms": ph,
+                                      "roofline": variant_roofline(B.info, ph, storage, kw)}
+            B.close()
+            del B
+            torch.cuda.empty_cache()
     if not args.no_solve:
         # time to a 1e-8 solve, b_i = |T_i| (z ~ 1 on the unit sphere), CG
         P = V[T]
