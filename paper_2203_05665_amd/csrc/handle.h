@@ -86,8 +86,10 @@ struct h2_handle_s {
   h2::DBuf adm_in_ptr, adm_in_blk, near_slot, near_in_ptr, near_in_slot, leaf_of_pos, scr_s, scr_n;
   // workspaces (sized for FP64 vectors, one right-hand side)
   h2::DBuf xc, yc, xhat, yhat;
-  // many-right-hand-side workspaces (FP32, grown on first use)
-  h2::DBuf mxc, myc, mxhat, myhat;
+  // many-right-hand-side workspaces (FP32, grown on first use) and the row order
+  // of the coupling kernels (built on first use)
+  h2::DBuf mxc, myc, mxhat, myhat, morder;
+  int64_t morder_items = 0;
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> events;     // pool

@@ -643,29 +643,90 @@ __global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const i
 }
 
 // ---------------------------------------------------------------- symmetric near field
-// Sum over lanes of p[j], delivered to lane j: 64 values per lane (32 for FP64,
-// where the two lane halves are added first and lane j & 31 receives column j),
-// by recursive halving: at each step a lane keeps the half of its values
-// selected by its lane bit, summed with the partner's copy of that half.  Both
-// halves are exchanged and the choice is made between the two sums, never
-// between array elements, so the array stays in registers.
-template <typename AT, int NV>
-__device__ inline AT transpose_reduce(AT (&p)[NV]) {
-  const int lane = threadIdx.x % 64;
-  if (NV == 32) {
-#pragma unroll
-    for (int q = 0; q < 32; ++q) p[q] += __shfl_xor(p[q], 32);
+// Cross-lane moves on gfx950 without the LDS crossbar.  xor_lane<S>(v) is the
+// value of lane l ^ S (S = 1, 2, 8: DPP quad permutes and a row rotation by 8 of
+// the 16-lane rows; S = 4: swizzle within 32 lanes).  swap_sum<S>(a, b) for
+// S = 32 / 16 exchanges the upper lane group of a with the lower group of b
+// (v_permlane32_swap / v_permlane16_swap) and adds: a lane whose bit S is clear
+// gets a + a[l ^ S], one whose bit S is set gets b[l ^ S] + b.
+template <int S>
+__device__ inline uint32_t xor_word(uint32_t v) {
+  if (S == 1) return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0xb1, 0xf, 0xf, false));
+  if (S == 2) return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x4e, 0xf, 0xf, false));
+  if (S == 8) return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x128, 0xf, 0xf, false));
+  return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(static_cast<int>(v), 0x101f));  // S == 4
+}
+template <int S>
+__device__ inline float xor_lane(float v) { return __uint_as_float(xor_word<S>(__float_as_uint(v))); }
+template <int S>
+__device__ inline double xor_lane(double v) {
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint64_t lo = xor_word<S>(static_cast<uint32_t>(u)), hi = xor_word<S>(static_cast<uint32_t>(u >> 32));
+  return __longlong_as_double(static_cast<long long>((hi << 32) | lo));
+}
+template <int S>
+__device__ inline void swap_words(uint32_t& a, uint32_t& b) {
+  if (S == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
   }
+}
+template <int S>
+__device__ inline float swap_sum(float a, float b) {
+  uint32_t x = __float_as_uint(a), y = __float_as_uint(b);
+  swap_words<S>(x, y);
+  return __uint_as_float(x) + __uint_as_float(y);
+}
+template <int S>
+__device__ inline double swap_sum(double a, double b) {
+  const uint64_t ua = static_cast<uint64_t>(__double_as_longlong(a)), ub = static_cast<uint64_t>(__double_as_longlong(b));
+  uint32_t al = static_cast<uint32_t>(ua), ah = static_cast<uint32_t>(ua >> 32);
+  uint32_t bl = static_cast<uint32_t>(ub), bh = static_cast<uint32_t>(ub >> 32);
+  swap_words<S>(al, bl);
+  swap_words<S>(ah, bh);
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(ah) << 32) | al)) +
+         __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(bh) << 32) | bl));
+}
+
+// one halving step over lane bit S: p[q] (q < S) becomes the sum, over the lane
+// pair {l, l ^ S}, of entry q (bit clear) or q + S (bit set)
+template <int S, typename AT, int NV>
+__device__ inline void halve(AT (&p)[NV], bool up) {
 #pragma unroll
-  for (int s = NV / 2; s >= 1; s >>= 1) {
-    const bool up = (lane & s) != 0;
-#pragma unroll
-    for (int q = 0; q < s; ++q) {
-      const AT lo = p[q] + __shfl_xor(p[q], s);
-      const AT hi = p[q + s] + __shfl_xor(p[q + s], s);
+  for (int q = 0; q < S; ++q) {
+    if (S >= 16) {
+      p[q] = swap_sum<S>(p[q], p[q + S]);
+    } else {
+      const AT lo = p[q] + xor_lane<S>(p[q]);
+      const AT hi = p[q + S] + xor_lane<S>(p[q + S]);
       p[q] = up ? hi : lo;
     }
   }
+}
+
+// Sum over lanes of p[j], delivered to lane j: 64 values per lane (32 for FP64,
+// where the two lane halves are added first and lane j & 31 receives column j),
+// by recursive halving: at each step a lane keeps the half of its values
+// selected by its lane bit, summed with the partner's copy of that half.
+template <typename AT, int NV>
+__device__ inline AT transpose_reduce(AT (&p)[NV]) {
+  const int lane = threadIdx.x % 64;
+  if (NV == 64) {
+    halve<32>(p, false);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) p[q] = swap_sum<32>(p[q], p[q]);  // both halves get the full sum
+  }
+  halve<16>(p, false);
+  halve<8>(p, (lane & 8) != 0);
+  halve<4>(p, (lane & 4) != 0);
+  halve<2>(p, (lane & 2) != 0);
+  halve<1>(p, (lane & 1) != 0);
   return p[0];
 }
 

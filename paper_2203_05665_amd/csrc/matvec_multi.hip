@@ -21,6 +21,9 @@
 // j = l % 32, i = (v % 4) + 4 (l / 32) + 8 (v / 4).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "handle.h"
 
 namespace h2 {
@@ -264,11 +267,14 @@ __global__ __launch_bounds__(256) void mtransfer_up(int count, const int32_t* __
 
 // y^_tau = sum_{(tau,sigma) admissible} S_{tau sigma} x^_sigma (assigns)
 template <int NT>
-__global__ __launch_bounds__(256) void mcoupling(int nc, const int64_t* __restrict__ ptr,
+__global__ __launch_bounds__(256) void mcoupling(int64_t nitems, const int32_t* __restrict__ order,
+                                                 const int64_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ col, const float* __restrict__ S,
                                                  const float* __restrict__ xhat, float* __restrict__ yhat) {
-  const int64_t tau = xcd_item(nc);
-  if (tau >= nc) return;
+  const int64_t it = xcd_item(nitems);
+  if (it >= nitems) return;
+  const int64_t tau = order[it];
+  if (tau < 0) return;
   constexpr int RP = 32 * NT;
   f32x16 acc[2][NT];
   zero(acc);
@@ -285,12 +291,14 @@ __global__ __launch_bounds__(256) void mcoupling(int nc, const int64_t* __restri
 // 2 ti + r / 16).  Point differences are (c_tau - c_sigma) + (o_tau - o_sigma)
 // with FP64 centres and FP32 offsets, as in the single-vector kernel.
 template <int NT, int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mcoupling_otf(int nc, const int64_t* __restrict__ ptr,
-                                                     const int32_t* __restrict__ col, const double* __restrict__ ctr,
-                                                     const float* __restrict__ off, const float* __restrict__ xhat,
-                                                     float* __restrict__ yhat) {
-  const int64_t tau = xcd_item(nc);
-  if (tau >= nc) return;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mcoupling_otf(
+    int64_t nitems, const int32_t* __restrict__ order, const int64_t* __restrict__ ptr,
+    const int32_t* __restrict__ col, const double* __restrict__ ctr, const float* __restrict__ off,
+    const float* __restrict__ xhat, float* __restrict__ yhat) {
+  const int64_t it = xcd_item(nitems);
+  if (it >= nitems) return;
+  const int64_t tau = order[it];
+  if (tau < 0) return;
   constexpr int RP = 32 * NT;
   const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
   const float* ot = off + tau * 12;
@@ -716,6 +724,32 @@ inline unsigned nblk(int64_t work, int per) {
   return static_cast<unsigned>(g < 1 ? 1 : g);
 }
 
+// Row clusters for the coupling kernels: 8 contiguous ranges of about equal
+// work (admissible blocks + 1 per row), one per XCD (xcd_item gives XCD x the
+// items [x L, (x + 1) L)), each padded with -1 to the common length L, a
+// multiple of 4.  Contiguous ranges keep neighbouring rows, which share column
+// clusters, on one L2; equal work keeps the eight XCDs busy until the end.
+std::vector<int32_t> balanced_rows(const Structure& S) {
+  const int32_t nc = S.nclusters;
+  double total = 0.0;
+  for (int32_t t = 0; t < nc; ++t) total += 1.0 + static_cast<double>(S.adm_ptr[t + 1] - S.adm_ptr[t]);
+  std::vector<int32_t> cut(9, nc);
+  cut[0] = 0;
+  double acc = 0.0;
+  int x = 1;
+  for (int32_t t = 0; t < nc && x < 8; ++t) {
+    acc += 1.0 + static_cast<double>(S.adm_ptr[t + 1] - S.adm_ptr[t]);
+    if (acc >= total * x / 8.0) cut[x++] = t + 1;
+  }
+  int64_t L = 4;
+  for (int c = 0; c < 8; ++c) L = std::max<int64_t>(L, cut[c + 1] - cut[c]);
+  L = (L + 3) / 4 * 4;
+  std::vector<int32_t> order(8 * L, -1);
+  for (int c = 0; c < 8; ++c)
+    for (int32_t t = cut[c]; t < cut[c + 1]; ++t) order[c * L + (t - cut[c])] = t;
+  return order;
+}
+
 template <int NT, typename XT>
 void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t ldy, double alpha, hipStream_t st) {
   constexpr int RP = 32 * NT;
@@ -751,25 +785,34 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
   }
+  // row clusters in XCD chunks of equal admissible-block count
+  if (H.morder.p == nullptr) {
+    const std::vector<int32_t> ord = balanced_rows(S);
+    H.morder.upload(ord);
+    H.morder_items = static_cast<int64_t>(ord.size());
+  }
+  const int64_t nit = H.morder_items;
+  const int32_t* ord = H.morder.as<int32_t>();
+  const unsigned gco = static_cast<unsigned>(nit / 4);  // a multiple of 8 workgroups
   if (H.otf) {
     const int64_t* ap = H.adm_ptr.as<int64_t>();
     const int32_t* ac = H.adm_col.as<int32_t>();
     const double* ctr = H.ctr.as<double>();
     const float* off = H.off32.as<float>();
     switch (H.P.kernel) {
-      case H2_LAPLACE: mcoupling_otf<NT, H2_LAPLACE><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh); break;
-      case H2_TEST_ONE: mcoupling_otf<NT, H2_TEST_ONE><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh); break;
+      case H2_LAPLACE: mcoupling_otf<NT, H2_LAPLACE><<<gco, 256, 0, st>>>(nit, ord, ap, ac, ctr, off, xh, yh); break;
+      case H2_TEST_ONE: mcoupling_otf<NT, H2_TEST_ONE><<<gco, 256, 0, st>>>(nit, ord, ap, ac, ctr, off, xh, yh); break;
       case H2_TEST_BILINEAR:
-        mcoupling_otf<NT, H2_TEST_BILINEAR><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh);
+        mcoupling_otf<NT, H2_TEST_BILINEAR><<<gco, 256, 0, st>>>(nit, ord, ap, ac, ctr, off, xh, yh);
         break;
       case H2_TEST_QUADRATIC:
-        mcoupling_otf<NT, H2_TEST_QUADRATIC><<<grid8(nc), 256, 0, st>>>(nc, ap, ac, ctr, off, xh, yh);
+        mcoupling_otf<NT, H2_TEST_QUADRATIC><<<gco, 256, 0, st>>>(nit, ord, ap, ac, ctr, off, xh, yh);
         break;
       default: throw Error(H2_EINVAL, "on-the-fly coupling supports real kernels only");
     }
   } else {
-    mcoupling<NT><<<grid8(nc), 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
-                                             H.Smat.as<float>(), xh, yh);
+    mcoupling<NT><<<gco, 256, 0, st>>>(nit, ord, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
+                                       H.Smat.as<float>(), xh, yh);
   }
   if (H.prof) {
     e2 = prof_event(H);
