@@ -252,3 +252,35 @@ def test_failures_are_reported():
     assert S.stats()["errors"] == {"unknown mesh 'nope'": 1}
     (f,) = S.failures()
     assert f["mesh"] == "nope" and f["error"].startswith("unknown mesh")
+
+
+def test_mixed_stream_of_wide_requests_has_no_failures():
+    """60 staggered requests (Laplace and Helmholtz kappa 2 / 4, 1..16 columns,
+    three meshes) through FP64 refinement over an FP32-rounded operator: every
+    request converges and nothing turns non-finite."""
+    be = DenseBackend(refine=True)
+    S = H2Server(be, mem_budget=1e12, max_active=32, clock=Clock())
+    for r in (2, 3):
+        S.register_mesh("sphere%d" % r, *I.icosphere(r))
+    S.register_mesh("cube8", *I.cube_surface(8))
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(60):
+        mesh = ["sphere2", "sphere3", "cube8"][rng.integers(3)]
+        n = S.meshes[mesh][1].shape[0]
+        kern = ["laplace", "helmholtz", "helmholtz"][rng.integers(3)]
+        kap = 4.0 if rng.random() < 0.5 else 2.0
+        r = int(rng.integers(1, 17))
+        B = rng.standard_normal((n, r))
+        if kern == "helmholtz":
+            B = B + 1j * rng.standard_normal((n, r))
+        reqs.append(S.submit(mesh, B, kernel=kern, kappa=kap if kern == "helmholtz" else 0.0, rtol=1e-8,
+                             arrival=0.002 * i * rng.random()))
+    S.run()
+    st = S.stats()
+    assert st["done"] == 60 and st["errors"] == {} and S.failures() == []
+    for q in reqs:
+        A = dense(be, S, q.mesh, q.kernel, q.kappa)
+        Z = q.result.numpy()
+        Bq = q.b.numpy().T
+        assert np.linalg.norm(A @ Z - Bq) <= 1.01e-8 * np.linalg.norm(Bq) * np.sqrt(Bq.shape[1])
