@@ -31,6 +31,7 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 __device__ inline f32x16 mfma(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
@@ -111,38 +112,6 @@ __device__ inline void mma_colA(const float* __restrict__ A, int lda, int mrows,
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
         for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma(av[ti][u], bv[tj][u], acc[ti][tj]);
-  }
-}
-
-// acc[ti][tj] += A(rows < mrows, 64) * B(64, cols), A column-major (lda), Bt
-// right-hand-side-major (element (kk, j) at Bt[j * 64 + kk]); in step (p, e)
-// lane half h covers kk = 8 p + 4 h + e.  Clamped loads and selects as above.
-template <int NT>
-__device__ inline void mma_colA_Bt(const float* __restrict__ A, int lda, int mrows, const float* __restrict__ Bt,
-                                   f32x16 (&acc)[2][NT]) {
-  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
-  const bool row0 = r < mrows, row1 = r + 32 < mrows;
-  const float* a0 = A + min(r, mrows - 1);
-  const float* a1 = A + min(r + 32, mrows - 1);
-#pragma unroll 2
-  for (int p = 0; p < 8; ++p) {
-    const int kk = 8 * p + 4 * h;
-    float av[2][4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float x0 = a0[(kk + e) * lda], x1 = a1[(kk + e) * lda];
-      av[0][e] = row0 ? x0 : 0.f;
-      av[1][e] = row1 ? x1 : 0.f;
-    }
-    f4v b[NT];
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj) b[tj] = ld4c(Bt + (32 * tj + r) * 64 + kk);
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma(av[ti][e], b[tj][e], acc[ti][tj]);
   }
 }
 
@@ -618,42 +587,6 @@ __device__ inline void mma64_rowA_c(const float* __restrict__ A, const float* __
   }
 }
 
-// C1 += Re(A) B, C2 += Im(A) B; A complex column-major (element (i, kk) at
-// A[2 (kk lda + i)] and +1), B position-major 32 columns; clamped loads as in mma_colA
-__device__ inline void mma_colA_c(const float* __restrict__ A, int lda, int mrows, const float* __restrict__ B,
-                                  int kcount, f32x16 (&C1)[2], f32x16 (&C2)[2]) {
-  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
-  const bool row0 = r < mrows, row1 = r + 32 < mrows;
-  const float* a0 = A + 2 * min(r, mrows - 1);
-  const float* a1 = A + 2 * min(r + 32, mrows - 1);
-  const float* b = B + r;
-  const int steps = min(32, kcount);
-#pragma unroll 2
-  for (int k0 = 0; k0 < steps; k0 += 4) {
-    float ar[2][4], ai[2][4], bv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int kk = k0 + u + 32 * h;
-      const bool ok = kk < kcount;
-      const int kc = min(kk, kcount - 1);
-      const float2 x0 = *reinterpret_cast<const float2*>(a0 + 2 * kc * lda);
-      const float2 x1 = *reinterpret_cast<const float2*>(a1 + 2 * kc * lda);
-      ar[0][u] = (ok && row0) ? x0.x : 0.f;
-      ai[0][u] = (ok && row0) ? x0.y : 0.f;
-      ar[1][u] = (ok && row1) ? x1.x : 0.f;
-      ai[1][u] = (ok && row1) ? x1.y : 0.f;
-      const float y = b[kc * 32];
-      bv[u] = ok ? y : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti) {
-        C1[ti] = mfma(ar[ti][u], bv[u], C1[ti]);
-        C2[ti] = mfma(ai[ti][u], bv[u], C2[ti]);
-      }
-  }
-}
 
 __global__ __launch_bounds__(256) void mcoupling_c(int nc, const int64_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col, const float* __restrict__ S,
@@ -675,47 +608,127 @@ __global__ __launch_bounds__(256) void mcoupling_c(int nc, const int64_t* __rest
     for (int v = 0; v < 16; ++v) out[(l % 32) * 64 + 32 * ti + acc_row(v, l)] = combine_c(c1[ti][v], c2[ti][v]);
 }
 
-__global__ __launch_bounds__(256) void mnear_backward_c(int nleaves, const int32_t* __restrict__ leaves,
-                                                        const int32_t* __restrict__ cbegin,
-                                                        const int32_t* __restrict__ cend,
-                                                        const int64_t* __restrict__ near_ptr,
-                                                        const int32_t* __restrict__ near_col,
-                                                        const int64_t* __restrict__ panel_off,
-                                                        const float* __restrict__ N, const float* __restrict__ Vb,
-                                                        const float* __restrict__ xc, const float* __restrict__ yhat,
-                                                        float* __restrict__ yc) {
-  const int64_t it = xcd_item(nleaves);
-  if (it >= nleaves) return;
-  const int l = threadIdx.x % 64;
-  const int32_t tau = leaves[it];
-  const int64_t b0 = cbegin[tau];
-  const int r = cend[tau] - cbegin[tau];
+// Complex near field + leaf backward on 16 x 16 tiles, as mnear_backward16: the
+// 32 real columns are [Xr | Xi] (tile tj = 0 real parts, 1 imaginary parts), A
+// is complex column-major (interleaved), C1 = Re(A) X and C2 = Im(A) X.  The real
+// output columns are C1[., 0] - C2[., 1] and the imaginary ones C1[., 1] + C2[., 0]:
+// the two terms of an output sit in the same lane, so no exchange is needed.
+// The real V times [y^r | y^i] adds to C1.
+template <int NTI>
+__device__ inline void near16c_leaf(int64_t it, int r, int64_t b0, int32_t tau, const int32_t* __restrict__ cbegin,
+                                    const int32_t* __restrict__ cend, const int64_t* __restrict__ near_ptr,
+                                    const int32_t* __restrict__ near_col, const int64_t* __restrict__ panel_off,
+                                    const float* __restrict__ N, const float* __restrict__ Vb,
+                                    const float* __restrict__ xc, const float* __restrict__ yhat,
+                                    float* __restrict__ yc) {
+  const int l = threadIdx.x % 64, li = l % 16, lk = l / 16;
+  int rowc[NTI];
+  bool rowok[NTI];
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti) {
+    rowok[ti] = 16 * ti + li < r;
+    rowc[ti] = min(16 * ti + li, r - 1);
+  }
+  f4v c1[NTI][2], c2[NTI][2];
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) c1[ti][tj] = c2[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
   const float* P = N + 2 * panel_off[it];
-  f32x16 c1[2], c2[2];
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) c1[ti][v] = c2[ti][v] = 0.f;
   int64_t colbase = 0;
   for (int64_t bb = near_ptr[it]; bb < near_ptr[it + 1]; ++bb) {
     const int32_t s = near_col[bb];
-    const int64_t s0 = cbegin[s];
     const int wdt = cend[s] - cbegin[s];
-    mma_colA_c(P + 2 * colbase * r, r, r, xc + s0 * 32, wdt, c1, c2);
+    const float* A = P + 2 * colbase * r;
+    const float* B = xc + static_cast<int64_t>(cbegin[s]) * 32 + li;
+    auto fetch = [&](int k0, float (&ar)[NTI], float (&ai)[NTI], float (&bv)[2]) {
+      const int kk = k0 + lk;
+      const bool ok = kk < wdt;
+      const int kc = ok ? kk : wdt - 1;
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        const float y = B[kc * 32 + 16 * tj];
+        bv[tj] = ok ? y : 0.f;
+      }
+#pragma unroll
+      for (int ti = 0; ti < NTI; ++ti) {
+        const f2v a = *reinterpret_cast<const f2v*>(A + 2 * (static_cast<int64_t>(kc) * r + rowc[ti]));
+        const bool use = ok && rowok[ti];
+        ar[ti] = use ? a.x : 0.f;
+        ai[ti] = use ? a.y : 0.f;
+      }
+    };
+    const int nsteps = (wdt + 3) >> 2;
+    float arn[NTI], ain[NTI], bvn[2];
+    fetch(0, arn, ain, bvn);
+    for (int st = 0; st < nsteps; ++st) {
+      float ar[NTI], ai[NTI], bv[2];
+#pragma unroll
+      for (int ti = 0; ti < NTI; ++ti) {
+        ar[ti] = arn[ti];
+        ai[ti] = ain[ti];
+      }
+      bv[0] = bvn[0];
+      bv[1] = bvn[1];
+      fetch(min(st + 1, nsteps - 1) * 4, arn, ain, bvn);
+#pragma unroll
+      for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          c1[ti][tj] = mfma16(ar[ti], bv[tj], c1[ti][tj]);
+          c2[ti][tj] = mfma16(ai[ti], bv[tj], c2[ti][tj]);
+        }
+    }
     colbase += wdt;
   }
-  // leaf backward: real V times [y^r | y^i] adds to the real-part accumulator only
-  f32x16 accv[2][1] = {{c1[0]}, {c1[1]}};
-  mma_colA_Bt<1>(Vb + b0 * 64, r, r, yhat + static_cast<int64_t>(tau) * 32 * 64, accv);
-  float* out = yc + b0 * 32 + l % 32;
+  // + V_tau [y^r | y^i]: A = Vb (column-major r x 64), B(kk, j) = y^_tau[j * 64 + kk]
+  const float* A = Vb + b0 * 64;
+  const float* Y = yhat + static_cast<int64_t>(tau) * 32 * 64 + li * 64;
+#pragma unroll 2
+  for (int k0 = 0; k0 < 64; k0 += 4) {
+    const int kk = k0 + lk;
+    float av[NTI], bv[2];
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+    for (int tj = 0; tj < 2; ++tj) bv[tj] = Y[16 * tj * 64 + kk];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = 32 * ti + acc_row(v, l);
-      const float val = combine_c(accv[ti][0][v], c2[ti][v]);   // every lane takes part in the exchange
-      if (i < r) out[i * 32] = val;
+    for (int ti = 0; ti < NTI; ++ti) {
+      const float x = A[kk * r + rowc[ti]];
+      av[ti] = rowok[ti] ? x : 0.f;
     }
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) c1[ti][tj] = mfma16(av[ti], bv[tj], c1[ti][tj]);
+  }
+  float* out = yc + b0 * 32 + li;
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * ti + 4 * lk + v;
+      if (i < r) {
+        out[i * 32] = c1[ti][0][v] - c2[ti][1][v];
+        out[i * 32 + 16] = c1[ti][1][v] + c2[ti][0][v];
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mnear_backward16c(
+    int nleaves, const int32_t* __restrict__ leaves, const int32_t* __restrict__ cbegin,
+    const int32_t* __restrict__ cend, const int64_t* __restrict__ near_ptr, const int32_t* __restrict__ near_col,
+    const int64_t* __restrict__ panel_off, const float* __restrict__ N, const float* __restrict__ Vb,
+    const float* __restrict__ xc, const float* __restrict__ yhat, float* __restrict__ yc) {
+  const int64_t it = xcd_item(nleaves);
+  if (it >= nleaves) return;
+  const int32_t tau = leaves[it];
+  const int64_t b0 = cbegin[tau];
+  const int r = cend[tau] - cbegin[tau];
+  switch ((r + 15) >> 4) {  // wave-uniform: one leaf per wave
+    case 1: near16c_leaf<1>(it, r, b0, tau, cbegin, cend, near_ptr, near_col, panel_off, N, Vb, xc, yhat, yc); break;
+    case 2: near16c_leaf<2>(it, r, b0, tau, cbegin, cend, near_ptr, near_col, panel_off, N, Vb, xc, yhat, yc); break;
+    case 3: near16c_leaf<3>(it, r, b0, tau, cbegin, cend, near_ptr, near_col, panel_off, N, Vb, xc, yhat, yc); break;
+    default: near16c_leaf<4>(it, r, b0, tau, cbegin, cend, near_ptr, near_col, panel_off, N, Vb, xc, yhat, yc); break;
+  }
 }
 
 inline unsigned nblk(int64_t work, int per) {
@@ -893,10 +906,10 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
     e3 = prof_event(H);
     H2_HIP(hipEventRecord(e3, st));
   }
-  mnear_backward_c<<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
-                                              H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
-                                              H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<float>(),
-                                              H.Vb.as<float>(), xc, yh, yc);
+  mnear_backward16c<<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                                H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
+                                                H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
   mpermute_out_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha);
   H2_HIP(hipGetLastError());
   if (H.prof) {
