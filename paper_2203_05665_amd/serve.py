@@ -158,7 +158,11 @@ class _CG:
 class _GMRES:
     """Restarted GMRES for all right-hand sides at once (independent Arnoldi
     processes advanced in lockstep; classical Gram-Schmidt twice as batched
-    matrix-vector products; complex Givens rotations), FP64 / complex128.
+    matrix-vector products; complex Givens rotations), FP64 / complex128.  The
+    basis vectors and products stay on the device; the Hessenberg columns, the
+    rotations and the residual estimates (a few numbers per right-hand side) are
+    kept on the host, so a step issues the Gram-Schmidt kernels, one
+    normalisation and one small device-to-host copy.
 
     phase "arnoldi": the next product is A q_j;  phase "residual": the next
     product is A X (true residual at the end of a restart cycle)."""
@@ -171,24 +175,27 @@ class _GMRES:
         self.tol, self.maxit, self.it = tol, maxit, 0
         self.X = torch.zeros_like(B)
         r, n = B.shape
-        self.nb = torch.linalg.vector_norm(B, dim=1)
+        self.nb = torch.linalg.vector_norm(B, dim=1).cpu().numpy()
         self.Q = torch.zeros((r, self.m + 1, n), dtype=B.dtype, device=B.device)
-        cdt = torch.complex128
-        self.H = torch.zeros((r, self.m + 1, self.m), dtype=cdt, device=B.device)
-        self.cs = torch.zeros((self.m, r), dtype=cdt, device=B.device)
-        self.sn = torch.zeros((self.m, r), dtype=cdt, device=B.device)
-        self.g = torch.zeros((self.m + 1, r), dtype=cdt, device=B.device)
+        self.H = np.zeros((r, self.m + 1, self.m), dtype=np.complex128)
+        self.cs = np.zeros((self.m, r), dtype=np.complex128)
+        self.sn = np.zeros((self.m, r), dtype=np.complex128)
+        self.g = np.zeros((self.m + 1, r), dtype=np.complex128)
         self.j = 0
         self._start(B)                       # X = 0: the residual is B itself
 
+    def _scale(self, v):
+        return v / np.where(self.nb > 0, self.nb, 1.0)
+
     def _start(self, R):
         t = self.t
-        beta = t.linalg.vector_norm(R, dim=1)
-        self._rel = beta / t.where(self.nb > 0, self.nb, t.ones_like(self.nb))
-        self.H.zero_()
-        self.g.zero_()
-        self.Q[:, 0, :] = R / t.where(beta > 0, beta, t.ones_like(beta)).to(R.dtype)[:, None]
-        self.g[0] = beta.to(self.g.dtype)
+        beta_d = t.linalg.vector_norm(R, dim=1)
+        self.Q[:, 0, :] = R / t.where(beta_d > 0, beta_d, t.ones_like(beta_d)).to(R.dtype)[:, None]
+        beta = beta_d.cpu().numpy()
+        self._rel = self._scale(beta)
+        self.H[:] = 0
+        self.g[:] = 0
+        self.g[0] = beta
         self.j = 0
         self.phase = "arnoldi"
 
@@ -202,49 +209,53 @@ class _GMRES:
             return
         j = self.j
         W = Y.clone()
-        hsum = t.zeros((W.shape[0], j + 1), dtype=self.H.dtype, device=W.device)
+        hsum = None
         for _ in range(2):                                           # classical Gram-Schmidt, twice
             h = self.ops.krylov_dots(self.Q, W, j + 1)               # (r, j+1) = <q_i, w>
             self.ops.krylov_update(self.Q, h, W, -1.0)
-            hsum += h.to(hsum.dtype)
+            hsum = h if hsum is None else hsum + h
         hn = t.linalg.vector_norm(W, dim=1)
-        hcol = t.zeros((self.m + 1, W.shape[0]), dtype=self.H.dtype, device=W.device)
-        hcol[: j + 1] = hsum.t()
-        hcol[j + 1] = hn.to(hcol.dtype)
         self.Q[:, j + 1, :] = W / t.where(hn > 0, hn, t.ones_like(hn)).to(W.dtype)[:, None]
-        for i in range(j):
+        cdt = t.complex128
+        hcol = t.cat([hsum.to(cdt), hn[:, None].to(cdt)], dim=1).cpu().numpy().T.copy()   # (j+2, r)
+        for i in range(j):                                           # previous rotations
             tmp = self.cs[i] * hcol[i] + self.sn[i] * hcol[i + 1]
-            hcol[i + 1] = -self.sn[i].conj() * hcol[i] + self.cs[i] * hcol[i + 1]
+            hcol[i + 1] = -np.conj(self.sn[i]) * hcol[i] + self.cs[i] * hcol[i + 1]
             hcol[i] = tmp
-        a, c = hcol[j], hcol[j + 1]
-        absa = a.abs()
-        den = t.sqrt(absa ** 2 + c.abs() ** 2)
+        a, c = hcol[j].copy(), hcol[j + 1].copy()
+        absa = np.abs(a)
+        den = np.sqrt(absa ** 2 + np.abs(c) ** 2)
         safe = absa > 0
-        one_r = t.ones_like(absa)
-        self.cs[j] = t.where(safe, (absa / t.where(den > 0, den, one_r)).to(a.dtype), t.zeros_like(a))
-        unit = t.where(safe, a / t.where(safe, absa, one_r).to(a.dtype), t.ones_like(a))
-        self.sn[j] = t.where(safe, unit * c.conj() / t.where(den > 0, den, one_r).to(a.dtype), t.ones_like(a))
-        hcol[j] = self.cs[j] * a + self.sn[j] * c
+        dsafe = np.where(den > 0, den, 1.0)
+        cs = np.where(safe, absa / dsafe, 0.0).astype(np.complex128)
+        unit = np.where(safe, a / np.where(safe, absa, 1.0), 1.0)
+        sn = np.where(safe, unit * np.conj(c) / dsafe, 1.0).astype(np.complex128)
+        self.cs[j], self.sn[j] = cs, sn
+        hcol[j] = cs * a + sn * c
         hcol[j + 1] = 0
-        self.g[j + 1] = -self.sn[j].conj() * self.g[j]
-        self.g[j] = self.cs[j] * self.g[j]
-        self.H[:, :, j] = hcol.t()
+        self.g[j + 1] = -np.conj(sn) * self.g[j]
+        self.g[j] = cs * self.g[j]
+        self.H[:, : j + 2, j] = hcol.T
         self.it += 1
         self.j += 1
-        self._rel = self.g[self.j].abs() / t.where(self.nb > 0, self.nb, t.ones_like(self.nb))
+        self._rel = self._scale(np.abs(self.g[self.j]))
 
     def close_cycle(self):
-        """Solve the small triangular systems, update X, and ask for the true residual."""
+        """Solve the small triangular systems (host), update X (device), and ask for
+        the true residual."""
         t = self.t
         k = self.j
         if k > 0:
-            Hk = self.H[:, :k, :k]                                    # (r, k, k)
-            gk = self.g[:k].t().unsqueeze(-1)                         # (r, k, 1)
-            diag = t.diagonal(Hk, dim1=1, dim2=2)
-            Hk = Hk + t.diag_embed(t.where(diag == 0, t.ones_like(diag), t.zeros_like(diag)))
-            y = t.linalg.solve_triangular(Hk, gk, upper=True)         # (r, k, 1)
-            yq = y.squeeze(-1) if self.X.is_complex() else y.squeeze(-1).real
-            self.ops.krylov_update(self.Q, yq.contiguous(), self.X, 1.0)
+            Hk = self.H[:, :k, :k]
+            r = Hk.shape[0]
+            y = np.zeros((r, k), dtype=np.complex128)
+            for i in range(k - 1, -1, -1):                           # back substitution, all columns at once
+                d = Hk[:, i, i]
+                acc = self.g[i] - np.einsum("rl,rl->r", Hk[:, i, i + 1:k], y[:, i + 1:k])
+                y[:, i] = acc / np.where(d == 0, 1.0, d)
+            yq = y if self.X.is_complex() else y.real
+            yd = t.as_tensor(np.ascontiguousarray(yq), device=self.X.device).to(self.X.dtype)
+            self.ops.krylov_update(self.Q, yd, self.X, 1.0)
         self.phase = "residual"
         self.j = 0
 
@@ -261,7 +272,7 @@ class _GMRES:
                 self.close_cycle()
 
     def relres(self):
-        return self._rel
+        return self.t.as_tensor(self._rel)
 
     def solution(self):
         return self.X

@@ -305,3 +305,19 @@ def test_symmetric_storage_solve():
         finally:
             A.close()
     assert np.linalg.norm(out[True] - out[False]) <= 1e-8 * np.linalg.norm(out[False])
+
+
+@pytest.mark.parametrize("case", [("sphere", 0, 4, 32), ("sphere", 1, 4, 64), ("sphere", 1, 4, 4), ("cube", 2, 4, 8)])
+@pytest.mark.parametrize("otf", [False, True])
+def test_symmetric_storage_edge_cases(case, otf):
+    """Symmetric storage on a single leaf (only a diagonal near block, no scratch),
+    on meshes without admissible blocks, and with one-to-four-triangle leaves."""
+    kind, level, m, leaf = case
+    H = oracle(kind, level, m, leaf)
+    x = I.random_vector(H.mesh.n, 23, "uniform")
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage="f64", coupling_otf=otf,
+                    symmetric=True)
+    try:
+        assert rel(gpu_matvec(A, x), H.matvec(x)) <= 1e-12
+    finally:
+        A.close()
