@@ -18,10 +18,14 @@ wave number) with 1..R right-hand sides.  The engine
 * reports per-request latency (arrival to result), p50/p99 and throughput.
 
 The product y <- y + G~ X is the library's (libh2mi355x.so through the ctypes
-binding); the Krylov vector algebra of each request (inner products, vector
-updates, Givens rotations) runs as FP64 tensor operations on the request's
-stream.  A backend object supplies the products, so the scheduler can also be
-driven by a CPU backend in tests.
+binding); the Krylov vector algebra of each request runs in FP64 on the
+request's stream.  Every reduction the scheduler or a solver takes a decision
+from (inner products, norms, the finiteness checks) goes through the backend's
+`dots` / `norms`: on the GPU these are the library's dot kernel, which reduces
+each output inside one workgroup in a fixed order, so the values are
+reproducible and need no communication between workgroups; elementwise updates
+are tensor operations.  A backend object supplies the products and these
+reductions, so the scheduler can also be driven by a CPU backend in tests.
 """
 from __future__ import annotations
 
@@ -87,17 +91,26 @@ class GPUBackend:
     def refine(self):
         return self.storage != "f64"
 
-    # batched Gram-Schmidt kernels of the library (current stream)
+    # reductions and batched Gram-Schmidt steps on the library's kernels (current stream)
     def krylov_dots(self, Q, W, nvec):
         return self.h2.h2_krylov_dots(Q, W, nvec)
 
     def krylov_update(self, Q, h, W, sign):
         self.h2.h2_krylov_update(Q, h.contiguous(), W, sign)
 
+    def dots(self, A, B):
+        """<a_c, b_c> for every row c of the (r, n) blocks A, B (conjugating A)."""
+        return self.h2.h2_krylov_dots(A[:, None, :], B, 1)[:, 0]
 
-class _TensorKrylov:
-    """Plain tensor versions of the batched Gram-Schmidt steps (for backends
-    without native kernels, e.g. the CPU test backend)."""
+    def norms(self, Z):
+        """Euclidean norm of every row of the (r, n) block Z (FP64)."""
+        d = self.h2.h2_krylov_dots(Z[:, None, :], Z, 1)[:, 0]
+        return self.torch.sqrt(d.real if d.is_complex() else d)
+
+
+class _TensorOps:
+    """Plain tensor versions of the reductions and Gram-Schmidt steps (for
+    backends without native kernels, e.g. the CPU test backend)."""
 
     @staticmethod
     def krylov_dots(Q, W, nvec):
@@ -107,6 +120,15 @@ class _TensorKrylov:
     @staticmethod
     def krylov_update(Q, h, W, sign):
         W += sign * (h[:, :, None] * Q[:, : h.shape[1]]).sum(1)
+
+    @staticmethod
+    def dots(A, B):
+        return ((A.conj() if A.is_complex() else A) * B).sum(1)
+
+    @staticmethod
+    def norms(Z):
+        import torch
+        return torch.linalg.vector_norm(Z, dim=1)
 
 
 # ---------------------------------------------------------------------------- Krylov state machines
@@ -120,13 +142,14 @@ class _TensorKrylov:
 class _CG:
     """Conjugate gradients for all right-hand sides at once (independent columns)."""
 
-    def __init__(self, torch, B, tol, maxit):
+    def __init__(self, torch, B, tol, maxit, ops):
         self.t = torch
+        self.ops = ops
         self.B = B
         self.X = torch.zeros_like(B)
         self.R = B.clone()
         self.P = B.clone()
-        self.rr = (B * B).sum(1)
+        self.rr = ops.dots(B, B)
         self.nb = torch.sqrt(self.rr)
         self.tol, self.maxit, self.it = tol, maxit, 0
 
@@ -135,12 +158,12 @@ class _CG:
 
     def advance(self, Q):
         t = self.t
-        pq = (self.P * Q).sum(1)
+        pq = self.ops.dots(self.P, Q)
         ok = pq > 0
         alpha = t.where(ok, self.rr / t.where(ok, pq, t.ones_like(pq)), t.zeros_like(pq))[:, None]
         self.X += alpha * self.P
         self.R -= alpha * Q
-        rr2 = (self.R * self.R).sum(1)
+        rr2 = self.ops.dots(self.R, self.R)
         okr = self.rr > 0
         beta = t.where(okr, rr2 / t.where(okr, self.rr, t.ones_like(self.rr)), t.zeros_like(rr2))[:, None]
         self.P = self.R + beta * self.P
@@ -175,7 +198,7 @@ class _GMRES:
         self.tol, self.maxit, self.it = tol, maxit, 0
         self.X = torch.zeros_like(B)
         r, n = B.shape
-        self.nb = torch.linalg.vector_norm(B, dim=1).cpu().numpy()
+        self.nb = ops.norms(B).cpu().numpy()
         self.Q = torch.zeros((r, self.m + 1, n), dtype=B.dtype, device=B.device)
         self.H = np.zeros((r, self.m + 1, self.m), dtype=np.complex128)
         self.cs = np.zeros((self.m, r), dtype=np.complex128)
@@ -189,7 +212,7 @@ class _GMRES:
 
     def _start(self, R):
         t = self.t
-        beta_d = t.linalg.vector_norm(R, dim=1)
+        beta_d = self.ops.norms(R)
         self.Q[:, 0, :] = R / t.where(beta_d > 0, beta_d, t.ones_like(beta_d)).to(R.dtype)[:, None]
         beta = beta_d.cpu().numpy()
         self._rel = self._scale(beta)
@@ -214,7 +237,7 @@ class _GMRES:
             h = self.ops.krylov_dots(self.Q, W, j + 1)               # (r, j+1) = <q_i, w>
             self.ops.krylov_update(self.Q, h, W, -1.0)
             hsum = h if hsum is None else hsum + h
-        hn = t.linalg.vector_norm(W, dim=1)
+        hn = self.ops.norms(W)
         self.Q[:, j + 1, :] = W / t.where(hn > 0, hn, t.ones_like(hn)).to(W.dtype)[:, None]
         cdt = t.complex128
         hcol = t.cat([hsum.to(cdt), hn[:, None].to(cdt)], dim=1).cpu().numpy().T.copy()   # (j+2, r)
@@ -333,6 +356,8 @@ class H2Server:
     def __init__(self, backend, mem_budget: float, max_active: int = 32, clock: Callable[[], float] = time.perf_counter):
         self.be = backend
         self.t = __import__("torch")
+        # reductions and Gram-Schmidt steps: the backend's own, else plain tensor operations
+        self.ops = backend if hasattr(backend, "norms") else _TensorOps
         self.budget = float(mem_budget)
         self.max_active = int(max_active)
         self.clock = clock
@@ -368,7 +393,7 @@ class H2Server:
             req.status, req.error = "failed", "right-hand side has %d rows, mesh has %d triangles" % (
                 b.shape[1], self.meshes[mesh][1].shape[0])
             self.finished.append(req)
-        elif not bool(t.isfinite(t.view_as_real(b) if cx else b).all()):
+        elif not np.isfinite(self.ops.norms(b).cpu().numpy()).all():
             req.status, req.error = "failed", "right-hand side is not finite"
             self.finished.append(req)
         else:
@@ -449,9 +474,8 @@ class H2Server:
     def _new_solver(self, q, rhs, tol):
         left = max(1, q.maxit - q.iterations)
         if q.kernel == "helmholtz":
-            ops = self.be if hasattr(self.be, "krylov_dots") else _TensorKrylov
-            return _GMRES(self.t, rhs, tol, left, q.restart, ops)
-        return _CG(self.t, rhs, tol, left)
+            return _GMRES(self.t, rhs, tol, left, q.restart, self.ops)
+        return _CG(self.t, rhs, tol, left, self.ops)
 
     def _operand(self, q) -> Tuple[object, bool]:
         """The vector block whose product this request needs next, and whether the
@@ -504,12 +528,13 @@ class H2Server:
 
     def _advance(self, q, Y):
         q.products += 1
-        bad = ~self.t.isfinite(self.t.view_as_real(Y) if Y.is_complex() else Y).all()
+        # per column: did the product return a non-finite entry (a non-finite norm)?
+        bad = ~self.t.isfinite(self.ops.norms(Y))
         q._bad_product = bad if q._bad_product is None else (q._bad_product | bad)
         if q._phase == "outer":
             R = q.b - Y
-            nb = self.t.linalg.vector_norm(q.b, dim=1)
-            q._resid = (self.t.linalg.vector_norm(R, dim=1) / self.t.where(nb > 0, nb, self.t.ones_like(nb)))
+            nb = self.ops.norms(q.b)
+            q._resid = self.ops.norms(R) / self.t.where(nb > 0, nb, self.t.ones_like(nb))
             q._outer_R = R
             return
         s = q._solver
@@ -523,7 +548,7 @@ class H2Server:
         for q in self.active:
             finished = False
             if q._phase == "outer":
-                rel = float(q._resid.max())
+                rel = _host_max(q._resid)
                 if not math.isfinite(rel):
                     q.status, q.error, finished = "failed", self._nonfinite(q, "outer residual"), True
                 elif rel <= q.rtol:
@@ -540,15 +565,15 @@ class H2Server:
                 s = q._solver
                 if isinstance(s, _GMRES):
                     if s.fresh():                   # true residual of the current iterate
-                        converged = float(s.relres().max()) <= s.tol
+                        converged = _host_max(s.relres()) <= s.tol
                         exhausted = s.it >= s.maxit
                     else:
                         s.step_done()
                         converged = exhausted = False
                 else:
-                    converged = float(s.relres().max()) <= s.tol
+                    converged = _host_max(s.relres()) <= s.tol
                     exhausted = s.it >= s.maxit
-                relmax = float(s.relres().max())
+                relmax = _host_max(s.relres())
                 if not math.isfinite(relmax):
                     q.status, q.error, finished = "failed", self._nonfinite(q, "inner residual"), True
                 elif converged:
@@ -579,7 +604,7 @@ class H2Server:
     def _nonfinite(self, q, where):
         """Failure message: which residual, and whether a product itself returned a
         non-finite entry (the library) or only the solver's arithmetic did."""
-        from_product = q._bad_product is not None and bool(q._bad_product)
+        from_product = q._bad_product is not None and bool(q._bad_product.cpu().numpy().any())
         detail = "a product returned a non-finite entry" if from_product else "all products were finite"
         s = q._solver
         if isinstance(s, _GMRES):
@@ -644,6 +669,13 @@ class H2Server:
                  "rhs": int(q.b.shape[0]), "iterations": q.iterations, "products": q.products,
                  "rel_residual": q.rel_residual, "error": q.error}
                 for q in self.finished if q.status in ("failed", "not_converged")]
+
+
+def _host_max(v) -> float:
+    """Largest entry of a small vector (tensor on any device, or array), taken on
+    the host (NaN if any entry is NaN)."""
+    a = v.cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)
+    return float(np.max(a)) if a.size else float("nan")
 
 
 class _nullcontext:
