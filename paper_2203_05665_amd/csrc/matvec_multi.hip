@@ -550,62 +550,83 @@ __global__ __launch_bounds__(256) void mpermute_out_c(int64_t n, int rcur, const
   }
 }
 
-__device__ inline float combine_c(float c1, float c2) {
-  const float other = __shfl_xor(c2, 16);
-  return (threadIdx.x % 32) < 16 ? c1 - other : c1 + other;
-}
+// Complex coupling on the real matrix cores.  With x^ held as 32 real columns
+// [Xr | Xi] and S = Sr + i Si (interleaved), the 32 output columns [Yr | Yi] are
+//   Sr [Xr | Xi] + Si [-Xi | Xr]:
+// the second right-hand operand is the first with its halves swapped and the
+// first half negated, so one set of accumulators holds the result and no lane
+// exchange is needed.  One half of a block (32 of its 64 K columns) in the K order
+// of mma64_rowA: per lane row 32 ti + r, columns kk .. kk + 3 with
+// kk = 8 (4 half + q) + 4 h.
+struct CHalf {
+  f4v u[2][4], w[2][4];  // S entries (re, im, re, im) of columns kk, kk + 1 / kk + 2, kk + 3
+  f4v b[4], bs[4];       // [Xr | Xi] and [-Xi | Xr] at rows kk .. kk + 3, column r
+};
 
-// C1[ti] += Re(A) B, C2[ti] += Im(A) B; A complex row-major 64 x 64 (interleaved),
-// Bt right-hand-side-major 32 columns; kk mapping as in mma64_rowA
-__device__ inline void mma64_rowA_c(const float* __restrict__ A, const float* __restrict__ Bt, f32x16 (&C1)[2],
-                                    f32x16 (&C2)[2]) {
+__device__ inline void load_half_c(const float* __restrict__ A, const float* __restrict__ Bt, int half, CHalf& d) {
   const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+  const int rs = (r + 16) % 32;
+  const float sg = r < 16 ? -1.f : 1.f;
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    float ar[2][4][4], ai[2][4][4];
-    f4v b[4];
+  for (int q = 0; q < 4; ++q) {
+    const int kk = 8 * (4 * half + q) + 4 * h;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = 8 * (4 * half + q) + 4 * h;
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti) {
-        const f4v u = ld4c(A + (32 * ti + r) * 128 + 2 * kk), w = ld4c(A + (32 * ti + r) * 128 + 2 * kk + 4);
-        ar[ti][q][0] = u.x; ai[ti][q][0] = u.y; ar[ti][q][1] = u.z; ai[ti][q][1] = u.w;
-        ar[ti][q][2] = w.x; ai[ti][q][2] = w.y; ar[ti][q][3] = w.z; ai[ti][q][3] = w.w;
-      }
-      b[q] = ld4c(Bt + r * 64 + kk);
+    for (int ti = 0; ti < 2; ++ti) {
+      d.u[ti][q] = ld4c(A + (32 * ti + r) * 128 + 2 * kk);
+      d.w[ti][q] = ld4c(A + (32 * ti + r) * 128 + 2 * kk + 4);
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int ti = 0; ti < 2; ++ti) {
-          C1[ti] = mfma(ar[ti][q][e], b[q][e], C1[ti]);
-          C2[ti] = mfma(ai[ti][q][e], b[q][e], C2[ti]);
-        }
+    d.b[q] = ld4c(Bt + r * 64 + kk);
+    d.bs[q] = sg * ld4c(Bt + rs * 64 + kk);
   }
 }
 
+__device__ inline void mma_half_c(const CHalf& d, f32x16 (&acc)[2]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        const f4v& src = e < 2 ? d.u[ti][q] : d.w[ti][q];
+        acc[ti] = mfma(src[2 * (e % 2)], d.b[q][e], acc[ti]);
+        acc[ti] = mfma(src[2 * (e % 2) + 1], d.bs[q][e], acc[ti]);
+      }
+}
 
-__global__ __launch_bounds__(256) void mcoupling_c(int nc, const int64_t* __restrict__ ptr,
-                                                   const int32_t* __restrict__ col, const float* __restrict__ S,
-                                                   const float* __restrict__ xhat, float* __restrict__ yhat) {
-  const int64_t tau = xcd_item(nc);
-  if (tau >= nc) return;
-  f32x16 C1[2][1], C2[2][1];
-  zero(C1);
-  zero(C2);
-  f32x16 c1[2] = {C1[0][0], C1[1][0]}, c2[2] = {C2[0][0], C2[1][0]};
-  const int64_t b1 = ptr[tau + 1];
-  for (int64_t b = ptr[tau]; b < b1; ++b)
-    mma64_rowA_c(S + b * 8192, xhat + static_cast<int64_t>(col[b]) * 32 * 64, c1, c2);
+// y^_tau = sum_{(tau,sigma) admissible} S_{tau sigma} x^_sigma, 16 complex columns
+// (assigns); row clusters in the XCD-balanced order of mcoupling.  Software
+// pipelined: the loads of the next half block are in flight while the current
+// half's products run (two half-block register sets, two waves per SIMD).
+__global__ __launch_bounds__(256) void mcoupling_c(int64_t nitems, const int32_t* __restrict__ order,
+                                                   const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                   const float* __restrict__ S, const float* __restrict__ xhat,
+                                                   float* __restrict__ yhat) {
+  const int64_t it = xcd_item(nitems);
+  if (it >= nitems) return;
+  const int64_t tau = order[it];
+  if (tau < 0) return;
+  f32x16 acc[2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[ti][v] = 0.f;
+  const int64_t b0 = ptr[tau], b1 = ptr[tau + 1];
+  CHalf P, Q;
+  if (b0 < b1) load_half_c(S + b0 * 8192, xhat + static_cast<int64_t>(col[b0]) * 2048, 0, P);
+  for (int64_t b = b0; b < b1; ++b) {
+    const float* Ab = S + b * 8192;
+    const float* Bb = xhat + static_cast<int64_t>(col[b]) * 2048;
+    load_half_c(Ab, Bb, 1, Q);
+    mma_half_c(P, acc);
+    if (b + 1 < b1) load_half_c(Ab + 8192, xhat + static_cast<int64_t>(col[b + 1]) * 2048, 0, P);
+    mma_half_c(Q, acc);
+  }
   const int l = threadIdx.x % 64;
   float* out = yhat + tau * 32 * 64;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) out[(l % 32) * 64 + 32 * ti + acc_row(v, l)] = combine_c(c1[ti][v], c2[ti][v]);
+    for (int v = 0; v < 16; ++v) out[(l % 32) * 64 + 32 * ti + acc_row(v, l)] = acc[ti][v];
 }
 
 // Complex near field + leaf backward on 16 x 16 tiles, as mnear_backward16: the
@@ -763,6 +784,15 @@ std::vector<int32_t> balanced_rows(const Structure& S) {
   return order;
 }
 
+// row clusters in XCD chunks of equal admissible-block count (built on first use)
+void ensure_row_order(h2_handle_s& H) {
+  if (H.morder.p == nullptr) {
+    const std::vector<int32_t> ord = balanced_rows(H.S);
+    H.morder.upload(ord);
+    H.morder_items = static_cast<int64_t>(ord.size());
+  }
+}
+
 template <int NT, typename XT>
 void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t ldy, double alpha, hipStream_t st) {
   constexpr int RP = 32 * NT;
@@ -798,12 +828,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
   }
-  // row clusters in XCD chunks of equal admissible-block count
-  if (H.morder.p == nullptr) {
-    const std::vector<int32_t> ord = balanced_rows(S);
-    H.morder.upload(ord);
-    H.morder_items = static_cast<int64_t>(ord.size());
-  }
+  ensure_row_order(H);
   const int64_t nit = H.morder_items;
   const int32_t* ord = H.morder.as<int32_t>();
   const unsigned gco = static_cast<unsigned>(nit / 4);  // a multiple of 8 workgroups
@@ -891,8 +916,10 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
   }
-  mcoupling_c<<<grid8(nc), 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<float>(),
-                                         xh, yh);
+  ensure_row_order(H);
+  mcoupling_c<<<static_cast<unsigned>(H.morder_items / 4), 256, 0, st>>>(
+      H.morder_items, H.morder.as<int32_t>(), H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<float>(),
+      xh, yh);
   if (H.prof) {
     e2 = prof_event(H);
     H2_HIP(hipEventRecord(e2, st));
