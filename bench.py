@@ -387,6 +387,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=220.0)
     ap.add_argument("--serve-deadline-s", type=float, default=150.0, help="cancel what is unfinished after this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--recompress", type=float, default=None, metavar="EPS",
+                    help="also time the algebraically recompressed representation (tolerance EPS)")
     ap.add_argument("--no-solve", "--no-fp64", dest="no_solve", action="store_true",
                     help="skip the solve comparison (FP64 vs mixed precision vs BF16 coupling)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a device copy of known size")
@@ -478,6 +480,39 @@ def main():
             B.close()
             del B
             torch.cuda.empty_cache()
+    if args.recompress is not None and not otf and storage in ("f32", "f64"):
+        # algebraic recompression of the stored representation (smaller uniform rank k')
+        log("bench: recompressed variant, eps %g" % args.recompress)
+        B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
+        y0 = torch.zeros_like(x)
+        B.matvec(x, y0)
+        rc = B.recompress(args.recompress)
+        yb = torch.zeros_like(x)
+        B.matvec(x, yb)
+        torch.cuda.synchronize()
+        change = float(np.linalg.norm((yb - y0).cpu().numpy()))
+        bound = float(np.sqrt(2.0 * rc["discarded"]) * np.linalg.norm(x.cpu().numpy()))
+        elb, profb = measure(B, x, yb, args.steps, args.warmup, torch, h2)
+        ph = {k: v[0] / max(1, v[1]) for k, v in profb.items()}
+        sb = {"f64": 8, "f32": 4}[storage]
+        inf = B.info
+        if ph["coupling"] >= ph["near"]:
+            nbytes, kern, ms = float(inf["s_blocks_stored"]) * inf["k"] ** 2 * sb, "coupling_any", ph["coupling"]
+        else:
+            nbytes, kern, ms = float(inf["near_entries_stored"] + inf["n"] * inf["k"]) * sb, "near_backward", ph["near"]
+        ach = nbytes / (ms * 1e-3) / 1e9
+        out.setdefault("variants", {})["recompressed"] = {
+            "value": args.steps / elb, "unit": "matvec/s", "ms_per_step": 1e3 * elb / args.steps,
+            "eps": args.recompress, "rank": rc["rank"], "recompress_s": rc["seconds"],
+            "bytes_V_E_S": [rc["bytes_before"], rc["bytes_after"]], "device_bytes": inf["bytes_total"],
+            "algorithmic_bytes": inf["matvec_bytes"], "phase_ms": ph,
+            "change_vs_stored": change, "frobenius_bound": bound,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": kern,
+                         "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": ms}}
+        B.close()
+        del B
+        torch.cuda.empty_cache()
     if not args.no_solve:
         # time to a 1e-8 solve, b_i = |T_i| (z ~ 1 on the unit sphere), CG
         P = V[T]

@@ -165,6 +165,43 @@ typedef struct {
 int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p,
              h2_solve_info* info, void* stream);
 
+/* Algebraic recompression (a smaller-rank H^2 matrix of the same block
+ * structure; the paper names such approximations as future work: the GCA-H^2
+ * variant in the section on distributed matrix setup, the recompression
+ * algorithm in the outlook).  The cluster bases are made orthonormal and
+ * nested (QR, bottom up), every cluster's basis is truncated to the dominant
+ * eigenvectors of the weight of all admissible blocks it carries, including
+ * those inherited from its ancestors, and the coupling matrices are projected.
+ * Every cluster is then padded to one rank k' and the handle's V, E and S are
+ * replaced in place: products (h2_matvec, h2_solve) use k' from then on, the
+ * near field is unchanged.
+ *   eps       relative tolerance per cluster: keep the eigenvalues of its
+ *             weight above eps^2 times the largest; 0 = orthogonalise only
+ *             (the represented matrix stays G~ up to rounding)
+ *   max_rank  0, or a cap on every cluster's rank
+ *   info      may be NULL; on success:
+ *               rank          k' (every cluster padded to it)
+ *               rank_before   k
+ *               discarded     sum of the discarded eigenvalues; the change
+ *                             satisfies ||G~ - G~'||_F^2 <= 2 * discarded
+ *               seconds       wall time
+ *               bytes_before / bytes_after   device bytes of V, E and S
+ * Requires a real kernel, H2_F64 or H2_F32 storage, stored coupling matrices
+ * (not H2_COUPLING_OTF) and full storage (not H2_SYMMETRIC); H2_EINVAL
+ * otherwise, or for eps < 0 / not finite, max_rank < 0.  Runs its device
+ * kernels on `stream` and returns after completion; the factorisations run on
+ * the host in FP64.  After recompression with k' != 64 several columns are
+ * applied one at a time. */
+typedef struct {
+  int64_t rank;
+  int64_t rank_before;
+  double discarded;
+  double seconds;
+  int64_t bytes_before;
+  int64_t bytes_after;
+} h2_recompress_info;
+int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* info, void* stream);
+
 int h2_info(h2_handle h, h2_stats* out);
 void h2_free(h2_handle h);
 const char* h2_last_error(void);

@@ -160,6 +160,7 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
         H->xhat.alloc(static_cast<size_t>(S.nclusters) * S.k * 8 * cw);
         H->yhat.alloc(static_cast<size_t>(S.nclusters) * S.k * 8 * cw);
         h2::assemble(*H);
+        H->kron = S.k == 64;
       }
     } catch (...) {
       delete H;
@@ -187,6 +188,15 @@ int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p, h2_s
     const int rc = h2::solve(*h, b, z, *p, info ? *info : tmp, static_cast<hipStream_t>(stream));
     if (rc == H2_ENOTCONV) return fail(rc, "solver did not reach the tolerance");
     return rc;
+  });
+}
+
+int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* info, void* stream) {
+  return guarded([&]() -> int {
+    if (!h) return fail(H2_EINVAL, "NULL handle");
+    h2_recompress_info tmp{};
+    h2::recompress(*h, eps, max_rank, info ? *info : tmp, static_cast<hipStream_t>(stream));
+    return H2_OK;
   });
 }
 
@@ -218,7 +228,7 @@ int h2_info(h2_handle h, h2_stats* out) {
     const double sb = h->P.storage == H2_F64 ? 8.0 : (h->P.storage == H2_F32 ? 4.0 : 2.0);
     const double k = S.k;
     // V twice; E twice, in Kronecker form (3 m^2 numbers per cluster) on the k = 64 path
-    const double e_per = S.k == 64 ? 3.0 * S.m * S.m : k * k;
+    const double e_per = h->kron ? 3.0 * S.m * S.m : k * k;
     const double v_e = 2.0 * S.n * k + 2.0 * e_per * (S.nclusters - 1);
     // every stored entry of S and of the near field is read once (symmetric storage: each
     // kept block serves both of its uses in the same pass)

@@ -81,6 +81,7 @@ struct h2_handle_s {
   // E_c = E_x (x) E_y (x) E_z: per cluster the three m x m one-dimensional factors,
   // E1[c][d][i][j] = l_j(xi_i) along axis d (i child point, j parent polynomial)
   h2::DBuf E1;
+  bool kron = false;  // transfers applied through E1 (interpolation bases, k = 64)
   // symmetric storage: incoming lists, near-field scratch slots, and the scratch
   // of the transposed products (sized for FP64 accumulation)
   h2::DBuf adm_in_ptr, adm_in_blk, near_slot, near_in_ptr, near_in_slot, leaf_of_pos, scr_s, scr_n;
@@ -112,6 +113,7 @@ void krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_
                  int64_t wr, void* h, hipStream_t st);
 void krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* h,
                    double sign, void* W, int64_t wr, hipStream_t st);
+void recompress(h2_handle_s& H, double eps, int max_rank, h2_recompress_info& info, hipStream_t st);
 hipEvent_t prof_event(h2_handle_s& H);
 void prof_record(h2_handle_s& H, int phase, hipEvent_t a, hipEvent_t b);
 }  // namespace h2

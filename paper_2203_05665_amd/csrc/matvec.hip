@@ -439,6 +439,41 @@ __global__ __launch_bounds__(256) void coupling_any(int nc, int k, const int64_t
   }
 }
 
+// Small k (recompressed bases, k <= RB <= 32): one wave per row cluster; the 64
+// lanes form 64 / RB slots of RB lanes, slot j takes the blocks ptr + j,
+// ptr + j + 64 / RB, ...; lane nu of a slot owns row nu of its block and issues
+// the whole row's loads at once (indices clamped to the last column, surplus
+// terms masked).  The slots' row sums are added by lane shuffles.
+template <int RB, typename SST, typename AT>
+__global__ __launch_bounds__(256) void coupling_small(int nc, int k, const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ col, const SST* __restrict__ S,
+                                                     const AT* __restrict__ xhat, AT* __restrict__ yhat) {
+  const int64_t tau = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
+  if (tau >= nc) return;  // uniform per wave
+  constexpr int NS = 64 / RB;
+  const int lane = threadIdx.x % 64, nu = lane % RB, slot = lane / RB;
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  const int nur = min(nu, k - 1);
+  AT acc = 0;
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau] + slot; b < b1; b += NS) {
+    const SST* Sb = S + b * kk + static_cast<int64_t>(nur) * k;
+    const AT* xs = xhat + static_cast<int64_t>(col[b]) * k;
+    AT a[RB], xv[RB];
+#pragma unroll
+    for (int mu = 0; mu < RB; ++mu) {
+      const int mc = min(mu, k - 1);
+      a[mu] = lds<SST, AT>(Sb + mc);
+      xv[mu] = xs[mc];
+    }
+#pragma unroll
+    for (int mu = 0; mu < RB; ++mu) acc += mu < k ? a[mu] * xv[mu] : AT(0);
+  }
+#pragma unroll
+  for (int o = RB; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
+  if (slot == 0 && nu < k) yhat[tau * k + nu] = acc;
+}
+
 // ---------------------------------------------------------------- coupling evaluated on the fly
 // s_{nu mu} = g(xi_{tau,nu}, xi_{sigma,mu}) (eq. coupling) from the tensor
 // Chebyshev points: xi - eta = (c_tau - c_sigma) + (o_tau - o_sigma) per axis,
@@ -1022,7 +1057,7 @@ void launch_up(h2_handle_s& H, AT* xh, hipStream_t st) {
     const int cnt = static_cast<int>(H.up_ptr[l + 1] - H.up_ptr[l]);
     if (cnt == 0) continue;
     const int32_t* list = H.up_list.as<int32_t>() + H.up_ptr[l];
-    if (S.k == 64)
+    if (H.kron)
       transfer_up_kron<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, list, H.child0.as<int32_t>(),
                                                                     H.child1.as<int32_t>(), H.E1.as<ST>(), xh);
     else
@@ -1037,7 +1072,7 @@ void launch_down(h2_handle_s& H, AT* yh, hipStream_t st) {
   for (int l = 0; l < S.depth; ++l) {
     const int first = S.level_ptr[l + 1], cnt = S.level_ptr[l + 2] - S.level_ptr[l + 1];
     if (cnt == 0) continue;
-    if (S.k == 64)
+    if (H.kron)
       transfer_down_kron<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(),
                                                                       H.E1.as<ST>(), yh);
     else
@@ -1081,6 +1116,12 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
   } else if (k == 64) {
     coupling64<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<SST>(),
                                            xh, yh);
+  } else if (k <= 16) {
+    coupling_small<16, SST, AT><<<blocks_for(nc, 4), 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(),
+                                                                   H.adm_col.as<int32_t>(), H.Smat.as<SST>(), xh, yh);
+  } else if (k <= 32) {
+    coupling_small<32, SST, AT><<<blocks_for(nc, 4), 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(),
+                                                                   H.adm_col.as<int32_t>(), H.Smat.as<SST>(), xh, yh);
   } else {
     coupling_any<SST, AT><<<nc, 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
                                              H.Smat.as<SST>(), xh, yh);

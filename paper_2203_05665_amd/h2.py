@@ -61,6 +61,11 @@ class h2_solve_info(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class h2_recompress_info(C.Structure):
+    _fields_ = [("rank", C.c_int64), ("rank_before", C.c_int64), ("discarded", C.c_double),
+                ("seconds", C.c_double), ("bytes_before", C.c_int64), ("bytes_after", C.c_int64)]
+
+
 _lib = None
 
 
@@ -88,8 +93,9 @@ def lib():
                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.h2_krylov_update.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
                                        C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]
+        L.h2_recompress.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(h2_recompress_info), C.c_void_p]
         for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
-                  "h2_krylov_dots", "h2_krylov_update"):
+                  "h2_krylov_dots", "h2_krylov_update", "h2_recompress"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -208,6 +214,14 @@ def h2_krylov_update(Q, h, W, sign=1.0, stream=None):
     return W
 
 
+def h2_recompress(h, eps, max_rank=0, stream=None) -> dict:
+    """Algebraic recompression in place (orthonormal nested bases truncated at the
+    relative tolerance eps per cluster, uniform rank k'); returns the info fields."""
+    info = h2_recompress_info()
+    _check(lib().h2_recompress(h, float(eps), int(max_rank), C.byref(info), _stream(stream)))
+    return {f: getattr(info, f) for f, _ in h2_recompress_info._fields_}
+
+
 def h2_info(h) -> dict:
     s = h2_stats()
     _check(lib().h2_info(h, C.byref(s)))
@@ -262,6 +276,12 @@ class H2Matrix:
         if y is None:
             y = torch.zeros_like(x)
         return h2_matvec(self.h, x, y, alpha, acc64, stream)
+
+    def recompress(self, eps, max_rank=0, stream=None):
+        """Replace V, E and S by a recompressed representation of rank k' (see h2_recompress)."""
+        out = h2_recompress(self.h, eps, max_rank, stream)
+        self.info = h2_info(self.h)
+        return out
 
     def solve(self, b, z=None, **kw):
         import torch

@@ -370,6 +370,7 @@ class H2Server:
         self._est: Dict[tuple, int] = {}
         self.ticks = 0
         self.batched_products = 0
+        self.busy_s = 0.0          # wall time of ticks that issued products (device work and host steps)
 
     # -- registry ---------------------------------------------------------------------
     def register_mesh(self, name: str, vertices, triangles):
@@ -492,6 +493,7 @@ class H2Server:
         self._admit(now)
         if not self.active:
             return 0
+        t_start = time.perf_counter()
         groups: Dict[tuple, List[Request]] = {}
         for q in self.active:
             X, acc64 = self._operand(q)
@@ -524,6 +526,7 @@ class H2Server:
             t.cuda.synchronize()
         self._retire()
         self.ticks += 1
+        self.busy_s += time.perf_counter() - t_start
         return len(outs)
 
     def _advance(self, q, Y):
@@ -659,6 +662,7 @@ class H2Server:
             "throughput_req_s": len(done) / span if span > 0 else None,
             "rhs_solved": int(sum(q.b.shape[0] for q in done)),
             "ticks": self.ticks, "batched_products": self.batched_products,
+            "busy_s": self.busy_s, "busy_frac": self.busy_s / span if span > 0 else None,
             "errors": dict(Counter(q.error for q in self.finished if q.status in ("failed", "cancelled"))),
         }
 

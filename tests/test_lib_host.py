@@ -130,3 +130,17 @@ def test_symmetric_storage_rejects_unsupported_settings():
         args.update(kw)
         with pytest.raises(h2.H2Error):
             h2.h2_free(h2.build_h2(V, T, **args))
+
+
+def test_recompression_argument_errors():
+    """h2_recompress refuses what it does not support before touching the device."""
+    V, T = I.icosphere(3)
+    h = h2.build_h2(V, T, order=4, leaf=32, eta=0.5, host_only=True)
+    try:
+        with pytest.raises(h2.H2Error) as e:
+            h2.h2_recompress(h, 1e-4, 0, stream=0)
+        assert e.value.code == h2.H2_EINVAL and "device" in h2.h2_last_error()
+    finally:
+        h2.h2_free(h)
+    with pytest.raises(h2.H2Error):
+        h2.h2_recompress(None, 1e-4, 0, stream=0)
