@@ -387,8 +387,12 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=220.0)
     ap.add_argument("--serve-deadline-s", type=float, default=150.0, help="cancel what is unfinished after this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--recompress", type=float, default=None, metavar="EPS",
-                    help="also time the algebraically recompressed representation (tolerance EPS)")
+    ap.add_argument("--recompress", type=float, default=1e-5, metavar="EPS",
+                    help="tolerance of the algebraically recompressed variant (default 1e-5)")
+    ap.add_argument("--no-recompress", dest="recompress", action="store_const", const=None,
+                    help="skip the recompressed variant")
+    ap.add_argument("--recompress-full-near", dest="recompress_sym_near", action="store_false",
+                    help="recompressed variant with the near field stored in full (default: one block per pair)")
     ap.add_argument("--no-solve", "--no-fp64", dest="no_solve", action="store_true",
                     help="skip the solve comparison (FP64 vs mixed precision vs BF16 coupling)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a device copy of known size")
@@ -483,7 +487,8 @@ def main():
     if args.recompress is not None and not otf and storage in ("f32", "f64"):
         # algebraic recompression of the stored representation (smaller uniform rank k')
         log("bench: recompressed variant, eps %g" % args.recompress)
-        B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
+        B = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage,
+                        symmetric_near=args.recompress_sym_near)
         y0 = torch.zeros_like(x)
         B.matvec(x, y0)
         rc = B.recompress(args.recompress)
@@ -497,13 +502,17 @@ def main():
         sb = {"f64": 8, "f32": 4}[storage]
         inf = B.info
         if ph["coupling"] >= ph["near"]:
-            nbytes, kern, ms = float(inf["s_blocks_stored"]) * inf["k"] ** 2 * sb, "coupling_any", ph["coupling"]
+            kern = "coupling_small" if inf["k"] <= 32 else "coupling_any"
+            nbytes, ms = float(inf["s_blocks_stored"]) * inf["k"] ** 2 * sb, ph["coupling"]
         else:
-            nbytes, kern, ms = float(inf["near_entries_stored"] + inf["n"] * inf["k"]) * sb, "near_backward", ph["near"]
+            kern = "near_backward_sym" if args.recompress_sym_near else "near_backward"
+            nbytes, ms = float(inf["near_entries_stored"] + inf["n"] * inf["k"]) * sb, ph["near"]
         ach = nbytes / (ms * 1e-3) / 1e9
         out.setdefault("variants", {})["recompressed"] = {
             "value": args.steps / elb, "unit": "matvec/s", "ms_per_step": 1e3 * elb / args.steps,
             "eps": args.recompress, "rank": rc["rank"], "recompress_s": rc["seconds"],
+            "near_field": "symmetric (one block per pair)" if args.recompress_sym_near else "full",
+            "rel_change_vs_stored": change / float(np.linalg.norm(y0.cpu().numpy())),
             "bytes_V_E_S": [rc["bytes_before"], rc["bytes_after"]], "device_bytes": inf["bytes_total"],
             "algorithmic_bytes": inf["matvec_bytes"], "phase_ms": ph,
             "change_vs_stored": change, "frobenius_bound": bound,

@@ -93,6 +93,11 @@ extern "C" {
                              storage, k = 64, leaves of at most 64 triangles; single right-hand
                              side kernels (several columns are applied one at a time).  With
                              H2_COUPLING_OTF only the near field is halved. */
+#define H2_SYMMETRIC_NEAR 8 /* the near-field half of H2_SYMMETRIC only: coupling blocks stay
+                             stored in full (so h2_recompress applies), near-field blocks are kept
+                             once per symmetric pair.  Real kernels, FP64 or FP32 storage, any
+                             order m, leaves of at most 64 triangles; single right-hand side
+                             kernels.  Together with H2_SYMMETRIC it is H2_SYMMETRIC. */
 
 typedef struct h2_handle_s* h2_handle;
 
@@ -111,7 +116,8 @@ typedef struct {
   double eta;     /* admissibility parameter of eq. admissibility             */
   int q_ss;       /* Gauss-Legendre order per axis of the Sauter-Schwab rules */
   int storage;    /* H2_F64, H2_F32, H2_F32_SBF16                             */
-  int flags;      /* 0 or any of H2_HOST_ONLY, H2_COUPLING_OTF, H2_SYMMETRIC  */
+  int flags;      /* 0 or any of H2_HOST_ONLY, H2_COUPLING_OTF, H2_SYMMETRIC,
+                     H2_SYMMETRIC_NEAR                                          */
 } h2_params;
 
 typedef struct {
@@ -187,7 +193,8 @@ int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p,
  *               seconds       wall time
  *               bytes_before / bytes_after   device bytes of V, E and S
  * Requires a real kernel, H2_F64 or H2_F32 storage, stored coupling matrices
- * (not H2_COUPLING_OTF) and full storage (not H2_SYMMETRIC); H2_EINVAL
+ * (not H2_COUPLING_OTF) and full coupling storage (not H2_SYMMETRIC; the
+ * near-field-only H2_SYMMETRIC_NEAR is fine); H2_EINVAL
  * otherwise, or for eps < 0 / not finite, max_rank < 0.  Runs its device
  * kernels on `stream` and returns after completion; the factorisations run on
  * the host in FP64.  After recompression with k' != 64 several columns are

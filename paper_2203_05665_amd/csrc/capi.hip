@@ -107,15 +107,18 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
       if (H->otf && (H->is_complex || P.storage == H2_F32_SBF16))
         throw h2::Error(H2_EINVAL, "on-the-fly coupling needs a real kernel and FP64 or FP32 storage");
       const bool sym = (P.flags & H2_SYMMETRIC) != 0;
+      const bool sym_near = sym || (P.flags & H2_SYMMETRIC_NEAR) != 0;
       if (sym && (H->is_complex || P.storage == H2_F32_SBF16 || P.order_m != 4))
         throw h2::Error(H2_EINVAL, "symmetric storage needs a real kernel, FP64 or FP32 storage and m = 4");
+      if (sym_near && (H->is_complex || P.storage == H2_F32_SBF16))
+        throw h2::Error(H2_EINVAL, "symmetric near-field storage needs a real kernel and FP64 or FP32 storage");
       h2::build_structure(H->S, mesh->vertices, mesh->nv, mesh->triangles, mesh->nt, P.order_m, P.leaf_size,
                           P.eta);
-      if (sym) {
+      if (sym_near) {
         for (int32_t c : H->S.leaves)
           if (H->S.cend[c] - H->S.cbegin[c] > 64)
             throw h2::Error(H2_EINVAL, "symmetric storage needs leaves of at most 64 triangles");
-        h2::make_symmetric(H->S, !H->otf, true);
+        h2::make_symmetric(H->S, sym && !H->otf, true);
       }
       if (!H->host_only) {
         H2_HIP(hipGetDevice(&H->device));
@@ -317,7 +320,7 @@ int h2_export(h2_handle h, int what, int64_t index, void* dst, int64_t cap) {
     };
     std::vector<double> v;
     if (what == H2_X_S && h->otf) return fail(H2_EINVAL, "coupling matrices are not stored (H2_COUPLING_OTF)");
-    if ((what == H2_X_S || what == H2_X_N) && (S.sym_s || S.sym_n))
+    if ((what == H2_X_S && S.sym_s) || (what == H2_X_N && S.sym_n))
       return fail(H2_EINVAL, "blocks are stored once per symmetric pair (H2_SYMMETRIC)");
     if (what == H2_X_V) {
       if (index < 0 || index >= nc || S.child0[index] >= 0) return fail(H2_EINVAL, "not a leaf cluster");

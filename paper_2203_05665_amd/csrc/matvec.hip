@@ -771,7 +771,7 @@ __device__ inline AT transpose_reduce(AT (&p)[NV]) {
 // off-diagonal block also yields G^T x|tau (column sums over the lanes), written
 // to the block's scratch slot; permute_out_sym adds the slots of each leaf.
 template <typename ST, typename AT>
-__global__ __launch_bounds__(256) void near_backward_sym(int nleaves, const int32_t* __restrict__ leaves,
+__global__ __launch_bounds__(256) void near_backward_sym(int nleaves, int k, const int32_t* __restrict__ leaves,
                                                          const int32_t* __restrict__ cbegin,
                                                          const int32_t* __restrict__ cend,
                                                          const int64_t* __restrict__ near_ptr,
@@ -832,10 +832,11 @@ __global__ __launch_bounds__(256) void near_backward_sym(int nleaves, const int3
     }
     colbase += w;
   }
-  // leaf backward: columns nu of V_tau, a quarter per wave
-  const ST* Vl = Vb + b0 * 64;
-  const AT yv = lane < 16 ? yhat[static_cast<int64_t>(tau) * 64 + 16 * wave + lane] : AT(0);
-  acc = stream_dot<ST, AT>(Vl + static_cast<int64_t>(16 * wave) * r + is, r, 16, yv, acc);
+  // leaf backward: columns nu of V_tau, a quarter per wave (k <= 64)
+  const ST* Vl = Vb + b0 * k;
+  const int kq = (k + 3) / 4, n0 = wave * kq, nv = min(k, n0 + kq) - n0;
+  const AT yv = lane < nv ? yhat[static_cast<int64_t>(tau) * k + n0 + lane] : AT(0);
+  acc = stream_dot<ST, AT>(Vl + static_cast<int64_t>(n0) * r + is, r, nv, yv, acc);
   part[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && lane < r) yc[b0 + lane] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
@@ -1136,7 +1137,7 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
     H2_HIP(hipEventRecord(e3, st));
   }
   if (S.sym_n) {
-    near_backward_sym<ST, AT><<<nl, 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+    near_backward_sym<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                                   H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
                                                   H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
                                                   H.near_slot.as<int64_t>(), H.Nmat.as<ST>(), H.Vb.as<ST>(), xc, yh,

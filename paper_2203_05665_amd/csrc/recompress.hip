@@ -48,9 +48,6 @@ __device__ inline void load_tile(double (*dst)[RP], const SST* __restrict__ src,
   }
 }
 
-__device__ inline double to_double(double v) { return v; }
-__device__ inline double to_double(float v) { return static_cast<double>(v); }
-
 // H_c = sum over the admissible blocks b of row c of S_b C_{col b} S_b^T
 template <typename SST>
 __global__ __launch_bounds__(256) void rc_gram(int nc, int k, const int64_t* __restrict__ ptr,
@@ -570,7 +567,7 @@ void recompress(h2_handle_s& H, double eps, int max_rank, h2_recompress_info& in
   if (H.host_only) throw Error(H2_EINVAL, "recompression needs a device structure");
   if (H.is_complex) throw Error(H2_EINVAL, "recompression is implemented for real kernels");
   if (H.otf) throw Error(H2_EINVAL, "recompression needs stored coupling matrices (not H2_COUPLING_OTF)");
-  if (H.S.sym_s || H.S.sym_n) throw Error(H2_EINVAL, "recompression needs full storage (not H2_SYMMETRIC)");
+  if (H.S.sym_s) throw Error(H2_EINVAL, "recompression needs full coupling storage (not H2_SYMMETRIC)");
   if (H.P.storage != H2_F64 && H.P.storage != H2_F32)
     throw Error(H2_EINVAL, "recompression needs H2_F64 or H2_F32 storage");
   if (!(eps >= 0.0) || !std::isfinite(eps)) throw Error(H2_EINVAL, "eps must be finite and >= 0");

@@ -22,7 +22,7 @@ H2_LAPLACE, H2_HELMHOLTZ, H2_TEST_ONE, H2_TEST_BILINEAR, H2_TEST_QUADRATIC = 0, 
 H2_F64, H2_F32, H2_F32_SBF16 = 0, 1, 2
 H2_R64, H2_R32, H2_C128, H2_C64 = 0, 1, 2, 3
 H2_ACC_F64 = 1
-H2_HOST_ONLY, H2_COUPLING_OTF, H2_SYMMETRIC = 1, 2, 4
+H2_HOST_ONLY, H2_COUPLING_OTF, H2_SYMMETRIC, H2_SYMMETRIC_NEAR = 1, 2, 4, 8
 H2_CG, H2_GMRES = 0, 1
 (H2_X_PERM, H2_X_CLUSTERS, H2_X_BOXES, H2_X_ADM, H2_X_NEAR, H2_X_DFS, H2_X_V, H2_X_E, H2_X_S,
  H2_X_N) = range(10)
@@ -119,7 +119,7 @@ def h2_last_error() -> str:
 
 
 def build_h2(vertices, triangles, kernel="laplace", kappa=0.0, order=4, leaf=64, eta=0.5, q_ss=4,
-             storage="f64", host_only=False, coupling_otf=False, symmetric=False):
+             storage="f64", host_only=False, coupling_otf=False, symmetric=False, symmetric_near=False):
     """Calls build_h2; returns the raw handle (int)."""
     V = np.ascontiguousarray(vertices, dtype=np.float64)
     T = np.ascontiguousarray(triangles, dtype=np.int32)
@@ -128,7 +128,7 @@ def build_h2(vertices, triangles, kernel="laplace", kappa=0.0, order=4, leaf=64,
     prm = h2_params(KERNELS[kernel] if isinstance(kernel, str) else int(kernel), float(kappa), int(order),
                     int(leaf), float(eta), int(q_ss), STORAGE[storage] if isinstance(storage, str) else int(storage),
                     (H2_HOST_ONLY if host_only else 0) | (H2_COUPLING_OTF if coupling_otf else 0) |
-                    (H2_SYMMETRIC if symmetric else 0))
+                    (H2_SYMMETRIC if symmetric else 0) | (H2_SYMMETRIC_NEAR if symmetric_near else 0))
     h = C.c_void_p()
     _check(lib().build_h2(C.byref(mesh), C.byref(prm), C.byref(h)))
     return h.value

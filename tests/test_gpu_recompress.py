@@ -167,3 +167,34 @@ def test_sphere327k_fp32_change_within_bound():
     print("recompression at 327,680 triangles:", info)
     assert info["rank"] < 64 and info["bytes_after"] < 0.7 * info["bytes_before"]
     assert np.linalg.norm(y1 - y0) <= np.sqrt(2.0 * info["discarded"]) * np.linalg.norm(x) + 2e-6 * np.linalg.norm(ya)
+
+
+@pytest.mark.parametrize("case", [("sphere", 3, 4, 32), ("cube", 8, 3, 32)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_symmetric_near_field_alone_and_recompressed(case, storage):
+    """H2_SYMMETRIC_NEAR: the near field stored once per pair (any k) gives G~ x;
+    recompressed on top it gives the oracle's recompressed product."""
+    H = oracle(*case)
+    O = oracle_rc(*case, 1e-4)
+    x = I.random_vector(H.mesh.n, 5, "normal")
+    ref, ref_c, ref_abs = H.matvec(x), O.matvec(x), H.matvec(np.abs(x))
+    kind, level, m, leaf = case
+    V, T = I.mesh_for(kind, level)
+    A = h2.H2Matrix(V, T, order=m, leaf=leaf, eta=0.5, storage=storage, symmetric_near=True)
+    try:
+        y = product(A, x)
+        info = A.recompress(1e-4)
+        yc = product(A, x)
+    finally:
+        A.close()
+    tol = 1e-12 if storage == "f64" else 1e-6
+    scale = np.linalg.norm(ref) if storage == "f64" else np.linalg.norm(ref_abs)
+    assert np.linalg.norm(y - ref) <= tol * scale
+    if storage == "f64":
+        assert info["rank"] == max(1, O.max_rank)
+        assert np.linalg.norm(yc - ref_c) <= 1e-10 * np.linalg.norm(ref_c)
+    else:
+        # FP32 S moves the weights' small eigenvalues: the rank may differ from the
+        # FP64 oracle's, the bound still holds
+        bound = np.sqrt(2.0 * info["discarded"]) * np.linalg.norm(x) + 1e-6 * np.linalg.norm(ref_abs)
+        assert np.linalg.norm(yc - ref) <= bound

@@ -144,3 +144,26 @@ def test_recompression_argument_errors():
         h2.h2_free(h)
     with pytest.raises(h2.H2Error):
         h2.h2_recompress(None, 1e-4, 0, stream=0)
+
+
+def test_symmetric_near_field_only():
+    """H2_SYMMETRIC_NEAR halves the near field and keeps every coupling block."""
+    V, T = I.icosphere(4)
+    full = h2.build_h2(V, T, order=3, leaf=32, eta=0.5, storage="f32", host_only=True)
+    symn = h2.build_h2(V, T, order=3, leaf=32, eta=0.5, storage="f32", host_only=True, symmetric_near=True)
+    try:
+        a, b = h2.h2_info(full), h2.h2_info(symn)
+        assert b["s_blocks_stored"] == a["s_blocks_stored"] == a["n_adm"]
+        assert b["near_entries_stored"] < 0.6 * a["near_entries_stored"]
+        assert b["n_near"] == a["n_near"] and b["near_entries"] == a["near_entries"]
+        assert np.array_equal(h2.h2_export(symn, h2.H2_X_ADM), h2.h2_export(full, h2.H2_X_ADM))
+        with pytest.raises(h2.H2Error):
+            h2.h2_export(symn, h2.H2_X_NEAR)
+    finally:
+        h2.h2_free(full)
+        h2.h2_free(symn)
+    for kw in (dict(kernel="helmholtz", kappa=2.0), dict(storage="f32_sbf16"), dict(leaf=100)):
+        args = dict(order=3, leaf=32, eta=0.5, storage="f32", host_only=True, symmetric_near=True)
+        args.update(kw)
+        with pytest.raises(h2.H2Error):
+            h2.h2_free(h2.build_h2(V, T, **args))
