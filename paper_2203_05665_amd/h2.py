@@ -74,8 +74,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIBPATH):
-            raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() "
-                               "(or python paper_2203_05665_amd/build_lib.py) first" % LIBPATH)
+            raise RuntimeError("HIP library %s is missing: build it first "
+                               "(python paper_2203_05665_amd/build_lib.py)" % LIBPATH)
         L = C.CDLL(LIBPATH)
         L.build_h2.argtypes = [C.POINTER(h2_mesh), C.POINTER(h2_params), C.POINTER(C.c_void_p)]
         L.h2_matvec.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
