@@ -81,9 +81,11 @@ extern "C" {
 #define H2_HOST_ONLY 1   /* build only the trees (no device work); for structure inspection */
 #define H2_COUPLING_OTF 2 /* do not store the coupling matrices: every product evaluates
                              s_{nu mu} = g(xi_{tau,nu}, xi_{sigma,mu}) (eq. coupling) from the
-                             clusters' interpolation points.  Real kernels only; FP64 storage
+                             clusters' interpolation points.  Real kernels: FP64 storage
                              evaluates in FP64, FP32 storage in FP32 from FP64 cluster-centre
-                             differences plus FP32 offsets. */
+                             differences plus FP32 offsets.  Helmholtz: FP32 storage and m = 4
+                             only, evaluated the same way in FP32 with the sine and cosine of
+                             kappa r by quadrant reduction and Taylor polynomials. */
 
 #define H2_SYMMETRIC 4    /* store one block of every symmetric pair (G~ = G~^T because test and
                              trial spaces coincide and g is symmetric): coupling blocks (tau,

@@ -104,8 +104,10 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
       H->host_only = (P.flags & H2_HOST_ONLY) != 0;
       H->is_complex = P.kernel == H2_HELMHOLTZ;
       H->otf = (P.flags & H2_COUPLING_OTF) != 0;
-      if (H->otf && (H->is_complex || P.storage == H2_F32_SBF16))
-        throw h2::Error(H2_EINVAL, "on-the-fly coupling needs a real kernel and FP64 or FP32 storage");
+      if (H->otf && !H->is_complex && P.storage == H2_F32_SBF16)
+        throw h2::Error(H2_EINVAL, "on-the-fly coupling needs FP64 or FP32 storage");
+      if (H->otf && H->is_complex && (P.storage != H2_F32 || P.order_m != 4))
+        throw h2::Error(H2_EINVAL, "on-the-fly Helmholtz coupling needs FP32 storage and m = 4");
       const bool sym = (P.flags & H2_SYMMETRIC) != 0;
       const bool sym_near = sym || (P.flags & H2_SYMMETRIC_NEAR) != 0;
       if (sym && (H->is_complex || P.storage == H2_F32_SBF16 || P.order_m != 4))

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "handle.h"
+#include "otf_math.h"
 
 namespace h2 {
 namespace {
@@ -559,6 +560,66 @@ __global__ __launch_bounds__(256) void coupling64_otf(int nc, const int64_t* __r
     acc = ((acc + part[0][nu]) + part[1][nu]) + part[2][nu];
     const AT scale = KIND == H2_LAPLACE ? AT(1.0 / (4.0 * 3.14159265358979323846)) : AT(1);
     yhat[static_cast<int64_t>(tau) * 64 + nu] = acc * scale;
+  }
+}
+
+// Helmholtz, k = 64, FP32 evaluation: as coupling64_otf with g = e^{i kappa r} / r
+// (times 1/(4 pi) at the end); per entry the squared distance, one reciprocal
+// square root, r, the sine and cosine of kappa r, and one complex multiply-add
+// with the wave-uniform x^_sigma (two planes).
+template <typename AT>
+__global__ __launch_bounds__(256) void coupling64c_otf(int nc, float kappa, const int64_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ ctr, const float* __restrict__ off,
+                                                       const AT* __restrict__ xhr, const AT* __restrict__ xhi,
+                                                       AT* __restrict__ yhr, AT* __restrict__ yhi) {
+  __shared__ AT part[2][3][64];
+  const int tau = blockIdx.x;
+  if (tau >= nc) return;
+  const int nu = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const float* ot = off + static_cast<int64_t>(tau) * 12;
+  const float ax = ot[nu & 3], ay = ot[4 + ((nu >> 2) & 3)], az = ot[8 + (nu >> 4)];
+  const double cx = ctr[3 * tau], cy = ctr[3 * tau + 1], cz = ctr[3 * tau + 2];
+  AT ar = 0, ai = 0;
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau] + w; b < b1; b += 4) {
+    const int64_t s = col[b];
+    const float* os = off + s * 12;
+    const AT* xr = xhr + s * 64;
+    const AT* xi = xhi + s * 64;
+    const float ex = static_cast<float>(cx - ctr[3 * s]) + ax, ey = static_cast<float>(cy - ctr[3 * s + 1]) + ay,
+                ez = static_cast<float>(cz - ctr[3 * s + 2]) + az;
+    float dx2[4], dy2[4], dz2[4], dyz[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float dx = ex - os[i], dy = ey - os[4 + i], dz = ez - os[8 + i];
+      dx2[i] = dx * dx;
+      dy2[i] = dy * dy;
+      dz2[i] = dz * dz;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dyz[i] = dy2[i & 3] + dz2[i >> 2];
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
+      const float d2 = dx2[j & 3] + dyz[j >> 2];
+      const float inv = rsq(d2);
+      float sn, cs;
+      sincos_phase(kappa * (d2 * inv), sn, cs);
+      const AT gr = static_cast<AT>(cs * inv), gi = static_cast<AT>(sn * inv);
+      ar += gr * xr[j] - gi * xi[j];
+      ai += gr * xi[j] + gi * xr[j];
+    }
+  }
+  if (w > 0) {
+    part[0][w - 1][nu] = ar;
+    part[1][w - 1][nu] = ai;
+  }
+  __syncthreads();
+  if (w == 0) {
+    const AT scale = AT(1.0 / (4.0 * 3.14159265358979323846));
+    yhr[static_cast<int64_t>(tau) * 64 + nu] = (((ar + part[0][0][nu]) + part[0][1][nu]) + part[0][2][nu]) * scale;
+    yhi[static_cast<int64_t>(tau) * 64 + nu] = (((ai + part[1][0][nu]) + part[1][1][nu]) + part[1][2][nu]) * scale;
   }
 }
 
@@ -1206,7 +1267,11 @@ void matvec_complex(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
   }
-  if (k == 64)
+  if (H.otf)
+    coupling64c_otf<AT><<<nc, 256, 0, st>>>(nc, static_cast<float>(H.P.kappa), H.adm_ptr.as<int64_t>(),
+                                            H.adm_col.as<int32_t>(), H.ctr.as<double>(), H.off32.as<float>(), xhr,
+                                            xhi, yhr, yhi);
+  else if (k == 64)
     coupling64c<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
                                             H.Smat.as<SST>(), xhr, xhi, yhr, yhi);
   else

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "otf_math.h"
 
 namespace h2 {
 namespace {
@@ -629,6 +630,90 @@ __global__ __launch_bounds__(256) void mcoupling_c(int64_t nitems, const int32_t
     for (int v = 0; v < 16; ++v) out[(l % 32) * 64 + 32 * ti + acc_row(v, l)] = acc[ti][v];
 }
 
+// Helmholtz coupling evaluated during the product, 16 complex columns: the
+// matrix-core scheme of mcoupling_c with the A operands (Re and Im of
+// e^{i kappa r} / r) computed per lane in the K order of mma64_rowA, from the
+// per-axis squared differences as in mcoupling_otf (x by e, y by P & 1, z by
+// (ti, P >> 1)); the sine and cosine by sincos_phase; times 1/(4 pi) at the end.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mcoupling_c_otf(
+    int64_t nitems, const int32_t* __restrict__ order, const int64_t* __restrict__ ptr,
+    const int32_t* __restrict__ col, const double* __restrict__ ctr, const float* __restrict__ off, float kappa,
+    const float* __restrict__ xhat, float* __restrict__ yhat) {
+  const int64_t it = xcd_item(nitems);
+  if (it >= nitems) return;
+  const int64_t tau = order[it];
+  if (tau < 0) return;
+  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
+  const int rs = (r + 16) % 32;
+  const float sg = r < 16 ? -1.f : 1.f;
+  const float* ot = off + tau * 12;
+  const float ax = ot[r % 4], ay = ot[4 + (r / 4) % 4];
+  const float az[2] = {ot[8 + r / 16], ot[10 + r / 16]};
+  const double cx = ctr[3 * tau], cy = ctr[3 * tau + 1], cz = ctr[3 * tau + 2];
+  f32x16 acc[2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[ti][v] = 0.f;
+  const int64_t b1 = ptr[tau + 1];
+  for (int64_t b = ptr[tau]; b < b1; ++b) {
+    const int64_t s = col[b];
+    const float* os = off + s * 12;
+    float px[4], py[2], pz[2][4];
+    const float ex = static_cast<float>(cx - ctr[3 * s]) + ax, ey = static_cast<float>(cy - ctr[3 * s + 1]) + ay;
+    const float dcz = static_cast<float>(cz - ctr[3 * s + 2]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d = ex - os[e];
+      px[e] = d * d;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const float d = ey - os[4 + 2 * j + h];
+      py[j] = d * d;
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int z = 0; z < 4; ++z) {
+        const float d = (dcz + az[ti]) - os[8 + z];
+        pz[ti][z] = d * d;
+      }
+    const float* Bt = xhat + s * 2048;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      f4v bv[4], bsv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = 8 * (4 * half + q) + 4 * h;
+        bv[q] = ld4c(Bt + r * 64 + kk);
+        bsv[q] = sg * ld4c(Bt + rs * 64 + kk);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int P = 4 * half + q;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti) {
+            const float d2 = px[e] + (py[P & 1] + pz[ti][P >> 1]);
+            const float inv = __builtin_amdgcn_rsqf(d2);
+            float sn, cs;
+            sincos_phase(kappa * (d2 * inv), sn, cs);
+            acc[ti] = mfma(cs * inv, bv[q][e], acc[ti]);
+            acc[ti] = mfma(sn * inv, bsv[q][e], acc[ti]);
+          }
+      }
+    }
+  }
+  const float scale = static_cast<float>(1.0 / (4.0 * 3.14159265358979323846));
+  float* out = yhat + tau * 32 * 64;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) out[(l % 32) * 64 + 32 * ti + acc_row(v, l)] = acc[ti][v] * scale;
+}
+
 // Complex near field + leaf backward on 16 x 16 tiles, as mnear_backward16: the
 // 32 real columns are [Xr | Xi] (tile tj = 0 real parts, 1 imaginary parts), A
 // is complex column-major (interleaved), C1 = Re(A) X and C2 = Im(A) X.  The real
@@ -917,9 +1002,14 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
     H2_HIP(hipEventRecord(e1, st));
   }
   ensure_row_order(H);
-  mcoupling_c<<<static_cast<unsigned>(H.morder_items / 4), 256, 0, st>>>(
-      H.morder_items, H.morder.as<int32_t>(), H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<float>(),
-      xh, yh);
+  if (H.otf)
+    mcoupling_c_otf<<<static_cast<unsigned>(H.morder_items / 4), 256, 0, st>>>(
+        H.morder_items, H.morder.as<int32_t>(), H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.ctr.as<double>(),
+        H.off32.as<float>(), static_cast<float>(H.P.kappa), xh, yh);
+  else
+    mcoupling_c<<<static_cast<unsigned>(H.morder_items / 4), 256, 0, st>>>(
+        H.morder_items, H.morder.as<int32_t>(), H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<float>(),
+        xh, yh);
   if (H.prof) {
     e2 = prof_event(H);
     H2_HIP(hipEventRecord(e2, st));
@@ -954,7 +1044,6 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
 
 bool matvec_multi_supported(const h2_handle_s& H) {
   if (H.host_only || H.P.storage != H2_F32 || H.S.k != 64) return false;
-  if (H.otf && H.is_complex) return false;
   if (H.S.sym_s || H.S.sym_n) return false;  // kept blocks are applied by the single-vector kernels
   for (int32_t c : H.S.leaves)
     if (H.S.cend[c] - H.S.cbegin[c] > 64) return false;  // one MFMA K-chunk per leaf

@@ -53,7 +53,11 @@ class GPUBackend:
         self.coupling_otf = coupling_otf
 
     def _otf(self, kernel):
-        return self.coupling_otf and kernel != "helmholtz" and self.storage in ("f32", "f64")
+        if not self.coupling_otf:
+            return False
+        if kernel == "helmholtz":          # FP32 evaluation of e^{i kappa r}/(4 pi r), m = 4
+            return self.storage == "f32" and self.order == 4
+        return self.storage in ("f32", "f64")
 
     def estimate(self, V, T, kernel, kappa):
         """Device bytes of the structure, from a host-only build of its trees."""

@@ -30,17 +30,27 @@ def cvec(n, seed):
     return I.random_vector(n, seed, "uniform") + 1j * I.random_vector(n, seed + 100, "uniform")
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32_otf"])
 @pytest.mark.parametrize("case", [("sphere", 3, 3, 32, 2.0), ("sphere", 3, 4, 16, 4.0), ("cube", 16, 4, 32, 4.0)])
 def test_helmholtz_matvec_matches_oracle(case, storage):
+    """f32_otf: FP32 storage with the coupling evaluated during the product (m = 4 only)."""
     kind, level, m, leaf, kappa = case
+    otf = storage == "f32_otf"
+    storage = "f32" if otf else storage
     H = oracle(kind, level, m, leaf, HELMHOLTZ, kappa)
+    if otf and m != 4:
+        with pytest.raises(h2.H2Error):
+            h2.H2Matrix(H.mesh.V, H.mesh.T, kernel="helmholtz", kappa=kappa, order=m, leaf=leaf, storage="f32",
+                        coupling_otf=True)
+        return
     L = oracle(kind, level, m, leaf, LAPLACE, 0.0)
     x = cvec(H.mesh.n, 3)
     ref = H.matvec(x)
     scale = L.matvec(np.abs(x))
     A = h2.H2Matrix(H.mesh.V, H.mesh.T, kernel="helmholtz", kappa=kappa, order=m, leaf=leaf, eta=0.5,
-                    storage=storage)
+                    storage=storage, coupling_otf=otf)
+    if otf:
+        assert A.info["s_blocks_stored"] == 0 and A.info["bytes_S"] < 1024
     try:
         for dt in (torch.complex128, torch.complex64):
             xd = torch.tensor(x, dtype=dt, device="cuda")
@@ -121,9 +131,10 @@ def test_helmholtz_cg_is_rejected():
         A.close()
 
 
+@pytest.mark.parametrize("otf", [False, True])
 @pytest.mark.parametrize("case", [("sphere", 3, 4, 16, 4.0), ("cube", 16, 4, 64, 2.0)])
 @pytest.mark.parametrize("nrhs", [2, 5, 16, 17, 33])
-def test_helmholtz_multi_rhs(case, nrhs):
+def test_helmholtz_multi_rhs(case, nrhs, otf):
     """Complex many-RHS product on the matrix cores: every column against the oracle."""
     kind, level, m, leaf, kappa = case
     H = oracle(kind, level, m, leaf, HELMHOLTZ, kappa)
@@ -131,7 +142,8 @@ def test_helmholtz_multi_rhs(case, nrhs):
     rng = np.random.default_rng(nrhs)
     X = rng.standard_normal((H.mesh.n, nrhs)) + 1j * rng.standard_normal((H.mesh.n, nrhs))
     Y0 = rng.standard_normal((H.mesh.n, nrhs)) + 1j * rng.standard_normal((H.mesh.n, nrhs))
-    A = h2.H2Matrix(H.mesh.V, H.mesh.T, kernel="helmholtz", kappa=kappa, order=m, leaf=leaf, eta=0.5, storage="f32")
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, kernel="helmholtz", kappa=kappa, order=m, leaf=leaf, eta=0.5, storage="f32",
+                    coupling_otf=otf)
     try:
         xd = torch.tensor(X, device="cuda").t().contiguous().t()
         yd = torch.tensor(Y0, device="cuda").t().contiguous().t()
@@ -143,3 +155,40 @@ def test_helmholtz_multi_rhs(case, nrhs):
         ref = Y0[:, j] - 0.5 * H.matvec(X[:, j])
         scale = 0.5 * L.matvec(np.abs(X[:, j]))
         assert np.linalg.norm(Y[:, j] - ref) <= 1e-6 * np.linalg.norm(scale), j
+
+
+def test_helmholtz_otf_full_size_sphere327k():
+    """327,680 triangles, kappa = 4, FP32: the product with the coupling evaluated
+    during the product agrees with the stored one within twice the FP32 bound
+    (both are G~ in FP32), for one column and for 16 columns."""
+    V, T = I.mesh_for("sphere", 7)
+    n = T.shape[0]
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((n, 16)) + 1j * rng.standard_normal((n, 16))
+    xd = torch.tensor(X.T.copy(), device="cuda").t()
+    out = {}
+    for otf in (False, True):
+        A = h2.H2Matrix(V, T, kernel="helmholtz", kappa=4.0, order=4, leaf=64, eta=0.5, storage="f32",
+                        coupling_otf=otf)
+        try:
+            Y = torch.zeros_like(xd)
+            A.matvec(xd, Y)
+            y1 = torch.zeros_like(xd[:, 0])
+            A.matvec(xd[:, 0].contiguous(), y1)
+            torch.cuda.synchronize()
+            out[otf] = (Y.cpu().numpy(), y1.cpu().numpy())
+        finally:
+            A.close()
+    # scale of the absolute terms: the Laplace matrix applied to |x_j| (|g_Helmholtz| = g_Laplace)
+    Lp = h2.H2Matrix(V, T, kernel="laplace", order=4, leaf=64, eta=0.5, storage="f32")
+    try:
+        ad = torch.tensor(np.abs(X).T.copy(), device="cuda").t()
+        sc = torch.zeros_like(ad)
+        Lp.matvec(ad, sc)
+        scale = np.linalg.norm(sc.cpu().numpy(), axis=0)
+    finally:
+        Lp.close()
+    (Ys, y1s), (Yo, y1o) = out[False], out[True]
+    assert np.linalg.norm(y1o - y1s) <= 2e-6 * scale[0]
+    for j in range(16):
+        assert np.linalg.norm(Yo[:, j] - Ys[:, j]) <= 2e-6 * scale[j], j
