@@ -429,21 +429,25 @@ __device__ inline void near16_leaf(int64_t it, int r, int64_t b0, int32_t tau, c
         av[ti] = (ok && rowok[ti]) ? x : 0.f;
       }
     };
-    // software pipeline: the next step's loads are in flight during this step's MFMAs
+    // software pipeline, NP steps deep: slot d holds the operands of step st + d;
+    // after its MFMAs a slot is refilled with step st + d + NP (clamped to the
+    // last step, so every load stays in range; the extra loads are never used)
+    constexpr int NP = TJ >= 4 ? 2 : 4;  // within the register budget of four waves per SIMD
     const int nsteps = (wdt + 3) >> 2;
-    float avn[NTI], bvn[TJ];
-    fetch(0, avn, bvn);
-    for (int st = 0; st < nsteps; ++st) {
-      float av[NTI], bv[TJ];
+    float av[NP][NTI], bv[NP][TJ];
 #pragma unroll
-      for (int ti = 0; ti < NTI; ++ti) av[ti] = avn[ti];
+    for (int d = 0; d < NP; ++d) fetch(min(d, nsteps - 1) * 4, av[d], bv[d]);
+    for (int st = 0; st < nsteps; st += NP) {
 #pragma unroll
-      for (int tj = 0; tj < TJ; ++tj) bv[tj] = bvn[tj];
-      fetch(min(st + 1, nsteps - 1) * 4, avn, bvn);
+      for (int d = 0; d < NP; ++d) {
+        if (st + d < nsteps) {
 #pragma unroll
-      for (int ti = 0; ti < NTI; ++ti)
+          for (int ti = 0; ti < NTI; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = mfma16(av[ti], bv[tj], acc[ti][tj]);
+            for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = mfma16(av[d][ti], bv[d][tj], acc[ti][tj]);
+          fetch(min(st + d + NP, nsteps - 1) * 4, av[d], bv[d]);
+        }
+      }
     }
     colbase += wdt;
   }
