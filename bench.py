@@ -43,6 +43,9 @@ OTF_F32_PEAK_TENTRY = 256 * 2.4e9 / (2.0 / 64 + 1.0 / 32) / 1e12
 # many right-hand sides: (mesh kind, level, order, leaf, storage, seed, nrhs)
 MULTI = {"cube786k_m4_r64": ("cube", 256, 4, 64, "f32", 4, 64)}
 MFMA_F32_PEAK_TFS = 157.3
+# Helmholtz products: (mesh kind, level, order, leaf, storage, seed, kappa)
+HELMHOLTZ = {"sphere327k_helmholtz_k4": ("sphere", 7, 4, 64, "f32", 2, 4.0),
+             "sphere1310k_helmholtz_k4": ("sphere", 8, 4, 64, "f32", 3, 4.0)}
 
 
 def log(*a):
@@ -236,6 +239,56 @@ def _walk(c):
         yield from _walk(ch)
 
 
+def bench_helmholtz(args):
+    """Helmholtz e^{i kappa r}/(4 pi r) products (complex vectors, FP32 storage): one
+    column and 16 columns, coupling stored and evaluated during the product."""
+    import numpy as np
+    import torch
+
+    import h2_inputs as I
+    from paper_2203_05665_amd import h2
+
+    kind, level, order, leaf, storage, seed, kappa = HELMHOLTZ[args.workload]
+    V, T = I.mesh_for(kind, level)
+    n = T.shape[0]
+    log("bench: %s n=%d m=%d leaf=%d storage=%s kappa=%g" % (args.workload, n, order, leaf, storage, kappa))
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((16, n)) + 1j * rng.standard_normal((16, n))
+    Xd = torch.tensor(X, device="cuda").t()            # n x 16, column-major
+    x1 = Xd[:, 0].contiguous()
+    res = {}
+    for otf in (False, True):
+        A = h2.H2Matrix(V, T, kernel="helmholtz", kappa=kappa, order=order, leaf=leaf, eta=0.5, storage=storage,
+                        coupling_otf=otf)
+        torch.cuda.synchronize()
+        for cols, xx in ((1, x1), (16, Xd)):
+            yy = torch.zeros_like(xx)
+            el, prof = measure(A, xx, yy, args.steps, args.warmup, torch, h2)
+            ph = {k: v[0] / max(1, v[1]) for k, v in prof.items()}
+            key = "%s_%dcol" % ("on_the_fly" if otf else "stored", cols)
+            res[key] = {"ms_per_product": 1e3 * el / args.steps, "rhs_products_per_s": cols * args.steps / el,
+                        "phase_ms": ph, "device_bytes": A.info["bytes_total"], "n_adm": A.info["n_adm"]}
+        A.close()
+        del A
+        torch.cuda.empty_cache()
+    st = res["stored_1col"]
+    sbytes = float(st["n_adm"]) * 64 * 64 * 8             # complex FP32 S of every admissible block
+    ach = sbytes / (st["phase_ms"]["coupling"] * 1e-3) / 1e9
+    out = {
+        "metric": "complex H2 matvecs/s", "value": 1e3 / st["ms_per_product"], "unit": "matvec/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": st["ms_per_product"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "mesh": "%s level %d" % (kind, level), "triangles": n,
+                   "order_m": order, "k": order ** 3, "leaf": leaf, "eta": 0.5, "storage": storage,
+                   "kernel": "helmholtz", "kappa": kappa},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "coupling64c",
+                     "algorithmic_bytes_per_launch": sbytes, "avg_launch_ms": st["phase_ms"]["coupling"]},
+        "results": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_multi(args):
     """Many right-hand sides in one call (matrix-core path)."""
     import torch
@@ -380,7 +433,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere1310k_m4_f32",
-                    choices=sorted(WORKLOADS) + sorted(OTF_WORKLOADS) + sorted(MULTI) + ["serve_mix"])
+                    choices=sorted(WORKLOADS) + sorted(OTF_WORKLOADS) + sorted(MULTI) + sorted(HELMHOLTZ)
+                    + ["serve_mix"])
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=32)
@@ -412,6 +466,8 @@ def main():
 
     if args.workload in MULTI:
         return bench_multi(args)
+    if args.workload in HELMHOLTZ:
+        return bench_helmholtz(args)
     if args.workload == "serve_mix":
         return bench_serve(args)
     otf = args.workload in OTF_WORKLOADS
