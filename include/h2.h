@@ -180,7 +180,8 @@ int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p,
  * nested (QR, bottom up), every cluster's basis is truncated to the dominant
  * eigenvectors of the weight of all admissible blocks it carries, including
  * those inherited from its ancestors, and the coupling matrices are projected.
- * Every cluster is then padded to one rank k' and the handle's V, E and S are
+ * Every cluster is then padded to one rank k' (the largest rank rounded up to a
+ * multiple of 4, but never above k) and the handle's V, E and S are
  * replaced in place: products (h2_matvec, h2_solve) use k' from then on, the
  * near field is unchanged.
  *   eps       relative tolerance per cluster: keep the eigenvalues of its

@@ -20,6 +20,8 @@
 // panel |tau| x (sum |sigma|), blocks in column-cluster order.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "handle.h"
 #include "otf_math.h"
 
@@ -445,7 +447,39 @@ __global__ __launch_bounds__(256) void coupling_any(int nc, int k, const int64_t
 // ptr + j + 64 / RB, ...; lane nu of a slot owns row nu of its block and issues
 // the whole row's loads at once (indices clamped to the last column, surplus
 // terms masked).  The slots' row sums are added by lane shuffles.
+// FP32 S with k a multiple of 4 (V4): rows are read as 16-byte vectors.
 template <int RB, typename SST, typename AT>
+__device__ inline AT row_dot_small(const SST* __restrict__ Sb, const AT* __restrict__ xs, int k) {
+  AT a[RB], xv[RB];
+#pragma unroll
+  for (int mu = 0; mu < RB; ++mu) {
+    const int mc = min(mu, k - 1);
+    a[mu] = lds<SST, AT>(Sb + mc);
+    xv[mu] = xs[mc];
+  }
+  AT acc = 0;
+#pragma unroll
+  for (int mu = 0; mu < RB; ++mu) acc += mu < k ? a[mu] * xv[mu] : AT(0);
+  return acc;
+}
+
+template <int RB>
+__device__ inline float row_dot_small_v4(const float* __restrict__ Sb, const float* __restrict__ xs, int k) {
+  f4v a[RB / 4], xv[RB / 4];
+#pragma unroll
+  for (int q = 0; q < RB / 4; ++q) {
+    const int qc = min(q, k / 4 - 1);
+    a[q] = *reinterpret_cast<const f4v*>(Sb + 4 * qc);
+    xv[q] = *reinterpret_cast<const f4v*>(xs + 4 * qc);
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int q = 0; q < RB / 4; ++q)
+    if (4 * q < k) acc += ((a[q].x * xv[q].x + a[q].y * xv[q].y) + a[q].z * xv[q].z) + a[q].w * xv[q].w;
+  return acc;
+}
+
+template <int RB, bool V4, typename SST, typename AT>
 __global__ __launch_bounds__(256) void coupling_small(int nc, int k, const int64_t* __restrict__ ptr,
                                                      const int32_t* __restrict__ col, const SST* __restrict__ S,
                                                      const AT* __restrict__ xhat, AT* __restrict__ yhat) {
@@ -460,15 +494,8 @@ __global__ __launch_bounds__(256) void coupling_small(int nc, int k, const int64
   for (int64_t b = ptr[tau] + slot; b < b1; b += NS) {
     const SST* Sb = S + b * kk + static_cast<int64_t>(nur) * k;
     const AT* xs = xhat + static_cast<int64_t>(col[b]) * k;
-    AT a[RB], xv[RB];
-#pragma unroll
-    for (int mu = 0; mu < RB; ++mu) {
-      const int mc = min(mu, k - 1);
-      a[mu] = lds<SST, AT>(Sb + mc);
-      xv[mu] = xs[mc];
-    }
-#pragma unroll
-    for (int mu = 0; mu < RB; ++mu) acc += mu < k ? a[mu] * xv[mu] : AT(0);
+    if constexpr (V4) acc += row_dot_small_v4<RB>(Sb, xs, k);
+    else acc += row_dot_small<RB, SST, AT>(Sb, xs, k);
   }
 #pragma unroll
   for (int o = RB; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
@@ -1178,12 +1205,26 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
   } else if (k == 64) {
     coupling64<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<SST>(),
                                            xh, yh);
-  } else if (k <= 16) {
-    coupling_small<16, SST, AT><<<blocks_for(nc, 4), 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(),
-                                                                   H.adm_col.as<int32_t>(), H.Smat.as<SST>(), xh, yh);
   } else if (k <= 32) {
-    coupling_small<32, SST, AT><<<blocks_for(nc, 4), 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(),
-                                                                   H.adm_col.as<int32_t>(), H.Smat.as<SST>(), xh, yh);
+    const int64_t* ap = H.adm_ptr.as<int64_t>();
+    const int32_t* ac = H.adm_col.as<int32_t>();
+    const SST* Sm = H.Smat.as<SST>();
+    const unsigned g = blocks_for(nc, 4);
+    constexpr bool f32 = std::is_same<SST, float>::value && std::is_same<AT, float>::value;
+    if constexpr (f32) {
+      if (k % 4 == 0) {
+        if (k <= 16) coupling_small<16, true, float, float><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
+        else coupling_small<32, true, float, float><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
+      } else if (k <= 16) {
+        coupling_small<16, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
+      } else {
+        coupling_small<32, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
+      }
+    } else if (k <= 16) {
+      coupling_small<16, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
+    } else {
+      coupling_small<32, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
+    }
   } else {
     coupling_any<SST, AT><<<nc, 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
                                              H.Smat.as<SST>(), xh, yh);

@@ -1,6 +1,7 @@
 // Algebraic recompression of the interpolation H^2 matrix: orthonormal nested
 // bases, truncated by the weights of everything a cluster carries, one uniform
-// rank k' for all clusters (smaller ranks padded with zero columns), after which
+// rank k' for all clusters, a multiple of 4 (smaller ranks padded with zero
+// columns), after which
 // the product runs on the same kernels with k' in place of k.
 //
 // The paper defers such approximations (the GCA-H^2 variant in the section on
@@ -492,8 +493,11 @@ void run(h2_handle_s& H, double eps, int cap, h2_recompress_info& info, hipStrea
       for (int i = r; i < rows; ++i) disc[c] += std::max(lam[i], 0.0);
     });
   }
+  // one rank for all clusters, rounded up to a multiple of 4 (rows of S'' and x^
+  // are then read as 16-byte vectors) unless that exceeds k; padding columns are zero
   int kp = 1;
   for (int c = 0; c < nc; ++c) kp = std::max(kp, rk[c]);
+  kp = std::min(k, (kp + 3) / 4 * 4);  // never above the rank it started from (k <= 64)
   double discarded = 0.0;
   for (int c = 0; c < nc; ++c) discarded += disc[c];
   // 4. coupling on the device: P_c = T_c R_c (rk x k), padded to 64 x 64
