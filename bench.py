@@ -308,7 +308,14 @@ def bench_multi(args):
     X = torch.tensor(I.random_vector(n, seed, "normal", nrhs=R), dtype=torch.float64, device="cuda")
     X = X.t().contiguous().t()
     Y = torch.zeros_like(X)
+    tuning = A.tune(R, "f64", reps=5)  # tile shapes for R columns, before the timed region
+    log("bench: tuning %s" % tuning)
     el, prof = measure(A, X, Y, args.steps, args.warmup, torch, h2)
+    try:
+        graph = graph_timing(A, X, Y, torch)  # the whole pass captured once, replayed
+        graph["rhs_matvec_per_s_median"] = R * graph["matvec_per_s_median"]
+    except Exception as e:  # reported, not fatal
+        graph = {"error": repr(e)}
     k = info["k"]
     # every step as a dense contraction over R columns: V twice, E twice (dense on
     # this path), S, near field
@@ -329,18 +336,20 @@ def bench_multi(args):
         "path": {"flops": flops_total, "TFLOPs": flops_total / (el / args.steps) / 1e12,
                  "phase_ms": {kk: v[0] / max(1, v[1]) for kk, v in prof.items()}, "build_s": build_s,
                  "device_bytes": info["bytes_total"]},
+        "tuning": tuning, "graph_replay": graph,
     }
     A.close()
     if not args.no_otf:
         log("bench: many right-hand sides with the coupling evaluated during the product")
         C = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage, coupling_otf=True)
         Yc = torch.zeros_like(X)
+        tuning_c = C.tune(R, "f64", reps=5)
         elc, profc = measure(C, X, Yc, args.steps, args.warmup, torch, h2)
         cms = profc["coupling"][0] / max(1, profc["coupling"][1])
         out["otf_variant"] = {
             "value": R * args.steps / elc, "unit": "rhs-matvec/s", "ms_per_step": 1e3 * elc / args.steps,
             "phase_ms": {kk: v[0] / max(1, v[1]) for kk, v in profc.items()},
-            "device_bytes": C.info["bytes_total"],
+            "device_bytes": C.info["bytes_total"], "tuning": tuning_c,
             "roofline": {"bound": "mfma", "achieved": coup_flops / (cms * 1e-3) / 1e12, "peak": MFMA_F32_PEAK_TFS,
                          "unit": "TFLOP/s", "frac": coup_flops / (cms * 1e-3) / 1e12 / MFMA_F32_PEAK_TFS,
                          "traffic": None, "kernel": "mcoupling_otf", "algorithmic_flops_per_launch": coup_flops,
@@ -553,6 +562,8 @@ def main():
         torch.cuda.synchronize()
         change = float(np.linalg.norm((yb - y0).cpu().numpy()))
         bound = float(np.sqrt(2.0 * rc["discarded"]) * np.linalg.norm(x.cpu().numpy()))
+        tuning_b = B.tune(1, "f64", reps=5)  # slot width of the small-rank coupling
+        log("bench: tuning %s" % tuning_b)
         elb, profb = measure(B, x, yb, args.steps, args.warmup, torch, h2)
         ph = {k: v[0] / max(1, v[1]) for k, v in profb.items()}
         sb = {"f64": 8, "f32": 4}[storage]
@@ -571,7 +582,7 @@ def main():
             "rel_change_vs_stored": change / float(np.linalg.norm(y0.cpu().numpy())),
             "bytes_V_E_S": [rc["bytes_before"], rc["bytes_after"]], "device_bytes": inf["bytes_total"],
             "algorithmic_bytes": inf["matvec_bytes"], "phase_ms": ph,
-            "change_vs_stored": change, "frobenius_bound": bound,
+            "change_vs_stored": change, "frobenius_bound": bound, "tuning": tuning_b,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": kern,
                          "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": ms}}

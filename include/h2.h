@@ -212,6 +212,51 @@ typedef struct {
 } h2_recompress_info;
 int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* info, void* stream);
 
+/* Tile-shape autotuning of the product y <- y + alpha G~ x (Algorithms 1-3 of the
+ * section on the matrix-vector multiplication; the tile shapes are this
+ * library's, not the paper's).  One knob decides the tiles of the path a call
+ * takes; several values compute the same product with different tiles (and a
+ * different summation order, within the storage precision):
+ *   H2_TUNE_PASS_COLUMNS  many right-hand sides (nrhs >= 2) with real kernels,
+ *                         H2_F32 storage, k = 64, full storage: right-hand sides
+ *                         per pass, 32 (one 32x32 MFMA column tile per wave in the
+ *                         coupling, two 16-column near-field tiles) or 64 (two and
+ *                         four).  Built-in rule: 32 if nrhs <= 32, else 64.
+ *   H2_TUNE_SMALL_SLOT    single-vector coupling with k <= 32 (recompressed
+ *                         bases): lanes per block-row slot of a wave, 16 (four
+ *                         blocks of a row cluster at a time, needs k <= 16) or 32
+ *                         (two).  Built-in rule: 16 if k <= 16, else 32.
+ * h2_tune runs the product the way h2_matvec(h, nrhs, dtype, ...) would, with
+ * every value of the knob that path has: one untimed and `reps` timed products
+ * each on library-owned vectors (allocated for the call), timed with HIP events
+ * on `stream`; it keeps the value with the smallest median time and fills info:
+ *   knob          the knob tuned, H2_TUNE_NONE if the path has no alternatives
+ *                 (complex kernels; single vectors with on-the-fly or symmetric
+ *                 coupling or k > 16; many right-hand sides that are applied one
+ *                 at a time with k > 16)
+ *   ncand         number of values timed (0 with H2_TUNE_NONE)
+ *   value[i]      the values, ms[i] their median milliseconds per product call
+ *   chosen        index of the value kept
+ * Synchronizes `stream`.  The choice stays with the handle for every later call
+ * until h2_set_tuning or h2_recompress (which resets H2_TUNE_SMALL_SLOT) changes
+ * it.  H2_EINVAL for nrhs < 1, reps < 1 or 1000 < reps, a host-only handle, or
+ * what h2_matvec rejects.
+ * h2_set_tuning sets a knob directly: value 0 restores the built-in rule;
+ * H2_EINVAL for an unknown knob or a value outside the list above (16 for
+ * H2_TUNE_SMALL_SLOT while k > 16). */
+#define H2_TUNE_NONE (-1)
+#define H2_TUNE_PASS_COLUMNS 0
+#define H2_TUNE_SMALL_SLOT 1
+typedef struct {
+  int knob;
+  int ncand;
+  int value[4];
+  double ms[4];
+  int chosen;
+} h2_tune_info;
+int h2_tune(h2_handle h, int nrhs, int dtype, int reps, h2_tune_info* info, void* stream);
+int h2_set_tuning(h2_handle h, int knob, int value);
+
 int h2_info(h2_handle h, h2_stats* out);
 void h2_free(h2_handle h);
 const char* h2_last_error(void);

@@ -21,7 +21,7 @@ ARCH = os.environ.get("H2_OFFLOAD_ARCH", "gfx950")
 
 HOST_SOURCES = ["structure.cpp", "quadrules.cpp"]
 HIP_SOURCES = ["assemble.hip", "matvec.hip", "matvec_multi.hip", "solve.hip", "krylov.hip", "recompress.hip",
-               "capi.hip"]
+               "tune.hip", "capi.hip"]
 
 
 def _hipcc():

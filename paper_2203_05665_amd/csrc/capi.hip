@@ -205,6 +205,23 @@ int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* inf
   });
 }
 
+int h2_tune(h2_handle h, int nrhs, int dtype, int reps, h2_tune_info* info, void* stream) {
+  return guarded([&]() -> int {
+    if (!h) return fail(H2_EINVAL, "NULL handle");
+    h2_tune_info tmp{};
+    h2::tune(*h, nrhs, dtype, reps, info ? *info : tmp, static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
+int h2_set_tuning(h2_handle h, int knob, int value) {
+  return guarded([&]() -> int {
+    if (!h) return fail(H2_EINVAL, "NULL handle");
+    h2::set_tuning(*h, knob, value);
+    return H2_OK;
+  });
+}
+
 int h2_info(h2_handle h, h2_stats* out) {
   return guarded([&]() -> int {
     if (!h || !out) return fail(H2_EINVAL, "NULL argument");

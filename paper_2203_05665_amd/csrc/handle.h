@@ -91,6 +91,9 @@ struct h2_handle_s {
   // of the coupling kernels (built on first use)
   h2::DBuf mxc, myc, mxhat, myhat, morder;
   int64_t morder_items = 0;
+  // tile choices (0: the built-in rule), set by h2_tune or h2_set_tuning
+  int tune_pass = 0;  // right-hand sides per many-RHS pass: 32 or 64
+  int tune_slot = 0;  // lanes per block-row slot of the small-k coupling: 16 or 32
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> events;     // pool
@@ -114,6 +117,8 @@ void krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_
 void krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* h,
                    double sign, void* W, int64_t wr, hipStream_t st);
 void recompress(h2_handle_s& H, double eps, int max_rank, h2_recompress_info& info, hipStream_t st);
+void tune(h2_handle_s& H, int nrhs, int dtype, int reps, h2_tune_info& info, hipStream_t st);
+void set_tuning(h2_handle_s& H, int knob, int value);
 hipEvent_t prof_event(h2_handle_s& H);
 void prof_record(h2_handle_s& H, int phase, hipEvent_t a, hipEvent_t b);
 }  // namespace h2

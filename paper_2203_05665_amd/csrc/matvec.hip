@@ -1210,17 +1210,19 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
     const int32_t* ac = H.adm_col.as<int32_t>();
     const SST* Sm = H.Smat.as<SST>();
     const unsigned g = blocks_for(nc, 4);
+    // slots of 16 lanes cover k <= 16; 32 lanes cover every k here (tuned choice)
+    const bool rb16 = k <= 16 && H.tune_slot != 32;
     constexpr bool f32 = std::is_same<SST, float>::value && std::is_same<AT, float>::value;
     if constexpr (f32) {
       if (k % 4 == 0) {
-        if (k <= 16) coupling_small<16, true, float, float><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
+        if (rb16) coupling_small<16, true, float, float><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
         else coupling_small<32, true, float, float><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
-      } else if (k <= 16) {
+      } else if (rb16) {
         coupling_small<16, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
       } else {
         coupling_small<32, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
       }
-    } else if (k <= 16) {
+    } else if (rb16) {
       coupling_small<16, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);
     } else {
       coupling_small<32, false, SST, AT><<<g, 256, 0, st>>>(nc, k, ap, ac, Sm, xh, yh);

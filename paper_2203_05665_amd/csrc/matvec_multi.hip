@@ -1057,7 +1057,7 @@ bool matvec_multi_supported(const h2_handle_s& H) {
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
                   double alpha, hipStream_t st) {
   const bool cx = dtype == H2_C128 || dtype == H2_C64;
-  const int rp = cx ? 32 : (nrhs <= 32 ? 32 : 64);
+  const int rp = cx ? 32 : H.tune_pass == 32 || H.tune_pass == 64 ? H.tune_pass : (nrhs <= 32 ? 32 : 64);
   const Structure& S = H.S;
   const size_t need_v = static_cast<size_t>(S.n) * rp * 4, need_h = static_cast<size_t>(S.nclusters) * 64 * rp * 4;
   if (H.mxc.bytes < need_v || H.mxhat.bytes < need_h) {

@@ -558,6 +558,7 @@ void run(h2_handle_s& H, double eps, int cap, h2_recompress_info& info, hipStrea
   H.E1.release();
   H.kron = false;
   S.k = kp;
+  H.tune_slot = 0;  // a slot width tuned for the old rank may not cover the new one
   info.rank = kp;
   info.rank_before = k;
   info.discarded = discarded;

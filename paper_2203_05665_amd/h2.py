@@ -27,6 +27,8 @@ H2_CG, H2_GMRES = 0, 1
 (H2_X_PERM, H2_X_CLUSTERS, H2_X_BOXES, H2_X_ADM, H2_X_NEAR, H2_X_DFS, H2_X_V, H2_X_E, H2_X_S,
  H2_X_N) = range(10)
 H2_PH_FORWARD, H2_PH_COUPLING, H2_PH_DOWN, H2_PH_NEAR, H2_PH_TOTAL, H2_NPHASE = 0, 1, 2, 3, 4, 5
+H2_TUNE_NONE, H2_TUNE_PASS_COLUMNS, H2_TUNE_SMALL_SLOT = -1, 0, 1
+TUNE_KNOBS = {"pass_columns": H2_TUNE_PASS_COLUMNS, "small_slot": H2_TUNE_SMALL_SLOT}
 
 KERNELS = {"laplace": H2_LAPLACE, "helmholtz": H2_HELMHOLTZ, "one": H2_TEST_ONE,
            "bilinear": H2_TEST_BILINEAR, "quadratic": H2_TEST_QUADRATIC}
@@ -66,6 +68,11 @@ class h2_recompress_info(C.Structure):
                 ("seconds", C.c_double), ("bytes_before", C.c_int64), ("bytes_after", C.c_int64)]
 
 
+class h2_tune_info(C.Structure):
+    _fields_ = [("knob", C.c_int), ("ncand", C.c_int), ("value", C.c_int * 4), ("ms", C.c_double * 4),
+                ("chosen", C.c_int)]
+
+
 _lib = None
 
 
@@ -94,8 +101,10 @@ def lib():
         L.h2_krylov_update.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
                                        C.c_void_p, C.c_double, C.c_void_p, C.c_int64, C.c_void_p]
         L.h2_recompress.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(h2_recompress_info), C.c_void_p]
+        L.h2_tune.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(h2_tune_info), C.c_void_p]
+        L.h2_set_tuning.argtypes = [C.c_void_p, C.c_int, C.c_int]
         for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
-                  "h2_krylov_dots", "h2_krylov_update", "h2_recompress"):
+                  "h2_krylov_dots", "h2_krylov_update", "h2_recompress", "h2_tune", "h2_set_tuning"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -222,6 +231,25 @@ def h2_recompress(h, eps, max_rank=0, stream=None) -> dict:
     return {f: getattr(info, f) for f, _ in h2_recompress_info._fields_}
 
 
+def h2_tune(h, nrhs=1, dtype="f64", reps=10, stream=None) -> dict:
+    """Time every tile choice of the product path for nrhs columns of the given
+    vector type ("f64" or "f32") on the handle and keep the fastest (see h2_tune
+    in include/h2.h); returns the knob, the values tried, their median ms and the
+    value kept."""
+    dt = {"f64": H2_R64, "f32": H2_R32, "c128": H2_C128, "c64": H2_C64}[dtype]
+    info = h2_tune_info()
+    _check(lib().h2_tune(h, int(nrhs), dt, int(reps), C.byref(info), _stream(stream)))
+    names = {v: k for k, v in TUNE_KNOBS.items()}
+    vals = [info.value[i] for i in range(info.ncand)]
+    return {"knob": names.get(info.knob), "values": vals, "ms": [info.ms[i] for i in range(info.ncand)],
+            "chosen": vals[info.chosen] if vals else None}
+
+
+def h2_set_tuning(h, knob, value):
+    """Set a tile knob ("pass_columns" or "small_slot") directly; 0 restores the rule."""
+    _check(lib().h2_set_tuning(h, TUNE_KNOBS[knob] if isinstance(knob, str) else int(knob), int(value)))
+
+
 def h2_info(h) -> dict:
     s = h2_stats()
     _check(lib().h2_info(h, C.byref(s)))
@@ -282,6 +310,13 @@ class H2Matrix:
         out = h2_recompress(self.h, eps, max_rank, stream)
         self.info = h2_info(self.h)
         return out
+
+    def tune(self, nrhs=1, dtype="f64", reps=10, stream=None):
+        """Pick the fastest tile shapes for products with nrhs columns (see h2_tune)."""
+        return h2_tune(self.h, nrhs, dtype, reps, stream)
+
+    def set_tuning(self, knob, value):
+        h2_set_tuning(self.h, knob, value)
 
     def solve(self, b, z=None, **kw):
         import torch

@@ -146,6 +146,36 @@ def test_recompression_argument_errors():
         h2.h2_recompress(None, 1e-4, 0, stream=0)
 
 
+def test_tuning_argument_errors():
+    """h2_tune and h2_set_tuning check their arguments before touching the device:
+    knob values outside the documented lists, slots of 16 lanes for k > 16, tuning
+    a host-only handle, bad nrhs / reps / dtype."""
+    V, T = I.icosphere(3)
+    h = h2.build_h2(V, T, order=3, leaf=32, eta=0.5, host_only=True)       # k = 27
+    try:
+        h2.h2_set_tuning(h, "pass_columns", 64)
+        h2.h2_set_tuning(h, "pass_columns", 0)
+        h2.h2_set_tuning(h, "small_slot", 32)
+        for knob, value in (("pass_columns", 48), ("small_slot", 8), ("small_slot", 16), (7, 32), (-1, 0)):
+            with pytest.raises(h2.H2Error) as e:
+                h2.h2_set_tuning(h, knob, value)
+            assert e.value.code == h2.H2_EINVAL
+        with pytest.raises(h2.H2Error) as e:
+            h2.h2_tune(h, 1, "f64", 5, stream=0)
+        assert e.value.code == h2.H2_EINVAL and "HOST_ONLY" in h2.h2_last_error()
+    finally:
+        h2.h2_free(h)
+    h = h2.build_h2(V, T, order=2, leaf=32, eta=0.5, host_only=True)       # k = 8
+    try:
+        h2.h2_set_tuning(h, "small_slot", 16)
+    finally:
+        h2.h2_free(h)
+    L = h2.lib()
+    info = h2.h2_tune_info()
+    assert L.h2_tune(None, 1, h2.H2_R64, 5, ctypes.byref(info), None) == h2.H2_EINVAL
+    assert L.h2_set_tuning(None, 0, 0) == h2.H2_EINVAL
+
+
 def test_symmetric_near_field_only():
     """H2_SYMMETRIC_NEAR halves the near field and keeps every coupling block."""
     V, T = I.icosphere(4)
