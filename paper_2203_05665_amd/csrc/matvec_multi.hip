@@ -369,6 +369,108 @@ __global__ __launch_bounds__(256) void mtransfer_down(int first, int count, cons
   store_hat<NT, true>(yhat + c * RP * 64, acc);
 }
 
+// Kronecker form of the two transfers (k = 64, interpolation bases):
+// E_c = E_x (x) E_y (x) E_z with E1[c][d][i][j] = l_j(xi_i) along axis d (i child
+// point, j parent polynomial), nu = nu_x + 4 nu_y + 16 nu_z.  One wave per output
+// cluster, lane = right-hand side: a lane holds the 64 coefficients of its column
+// in registers (one 256-byte row of x^, read as 16-byte vectors), so every axis
+// step is 16 register-local 4 x 4 products with the wave-uniform factor entries
+// (scalar loads) and no lane exchange.  A transfer reads 48 factor numbers
+// instead of a dense 64 x 64 E and takes 12 multiply-adds per coefficient
+// instead of 64: it is bound by the x^ / y^ rows it moves.  With 32 columns per
+// pass the upper half of the wave idles.
+// One axis step in place: v[nu] <- sum_i a(o, i) v[nu with digit d = i], o = the
+// digit d of nu; a(o, i) = E_d[i][o] (up, transposed) or E_d[o][i] (down).
+template <int D, bool TRANSPOSE>
+__device__ inline void kron_axis_regs(float (&v)[64], const float* __restrict__ e) {
+  constexpr int S = 1 << (2 * D);
+#pragma unroll
+  for (int line = 0; line < 16; ++line) {
+    const int b = D == 0 ? 4 * line : D == 1 ? (line & 3) + 16 * (line >> 2) : line;
+    float t[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = v[b + i * S];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      float r = 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r += e[TRANSPOSE ? 4 * i + o : 4 * o + i] * t[i];
+      v[b + o * S] = r;
+    }
+  }
+}
+
+__device__ inline void load_row64(const float* __restrict__ p, float (&v)[64]) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const f4v t = ld4c(p + 4 * q);
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
+  }
+}
+
+// x^_c = E_c0^T x^_c0 + E_c1^T x^_c1 for the parents of one level
+template <int NT>
+__global__ __launch_bounds__(256) void mtransfer_up_kron(int count, const int32_t* __restrict__ list,
+                                                         const int32_t* __restrict__ child0,
+                                                         const int32_t* __restrict__ child1,
+                                                         const float* __restrict__ E1, float* __restrict__ xhat) {
+  const int it = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_item(count)));
+  if (it >= count) return;  // uniform per wave
+  constexpr int RP = 32 * NT;
+  const int j = threadIdx.x % 64;
+  if (j >= RP) return;
+  const int32_t c = __builtin_amdgcn_readfirstlane(list[it]);
+  float acc[64];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int64_t ch = __builtin_amdgcn_readfirstlane(a == 0 ? child0[c] : child1[c]);
+    const float* e = E1 + ch * 48;
+    float v[64];
+    load_row64(xhat + (ch * RP + j) * 64, v);
+    kron_axis_regs<0, true>(v, e);
+    kron_axis_regs<1, true>(v, e + 16);
+    kron_axis_regs<2, true>(v, e + 32);
+#pragma unroll
+    for (int i = 0; i < 64; ++i) acc[i] = a == 0 ? v[i] : acc[i] + v[i];
+  }
+  float* out = xhat + (static_cast<int64_t>(c) * RP + j) * 64;
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    *reinterpret_cast<f4v*>(out + 4 * q) = f4v{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+}
+
+// y^_c += E_c y^_parent(c) for the clusters of one level
+template <int NT>
+__global__ __launch_bounds__(256) void mtransfer_down_kron(int first, int count, const int32_t* __restrict__ parent,
+                                                           const float* __restrict__ E1, float* __restrict__ yhat) {
+  const int it = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_item(count)));
+  if (it >= count) return;  // uniform per wave
+  constexpr int RP = 32 * NT;
+  const int j = threadIdx.x % 64;
+  if (j >= RP) return;
+  const int64_t c = first + it;
+  const int64_t p = __builtin_amdgcn_readfirstlane(parent[c]);
+  const float* e = E1 + c * 48;
+  float v[64];
+  load_row64(yhat + (p * RP + j) * 64, v);
+  kron_axis_regs<0, false>(v, e);
+  kron_axis_regs<1, false>(v, e + 16);
+  kron_axis_regs<2, false>(v, e + 32);
+  float* out = yhat + (c * RP + j) * 64;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    f4v t = ld4c(out + 4 * q);
+    t.x += v[4 * q];
+    t.y += v[4 * q + 1];
+    t.z += v[4 * q + 2];
+    t.w += v[4 * q + 3];
+    *reinterpret_cast<f4v*>(out + 4 * q) = t;
+  }
+}
+
 // Y|tau = sum_{(tau,sigma) inadmissible} G|tau x sigma X|sigma + V_tau y^_tau for
 // every leaf (all leaves hold at most 64 triangles on this path), on 16 x 16
 // tiles (v_mfma_f32_16x16x4f32): one wave per leaf.  Lane l supplies
@@ -910,8 +1012,13 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
   for (int lv = S.depth - 1; lv >= 0; --lv) {
     const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
     if (cnt == 0) continue;
-    mtransfer_up<NT><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
-                                                 H.child0.as<int32_t>(), H.child1.as<int32_t>(), H.ET.as<float>(), xh);
+    if (H.kron)
+      mtransfer_up_kron<NT><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
+                                                        H.child0.as<int32_t>(), H.child1.as<int32_t>(),
+                                                        H.E1.as<float>(), xh);
+    else
+      mtransfer_up<NT><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
+                                                   H.child0.as<int32_t>(), H.child1.as<int32_t>(), H.ET.as<float>(), xh);
   }
   if (H.prof) {
     e1 = prof_event(H);
@@ -948,7 +1055,10 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
   for (int lv = 0; lv < S.depth; ++lv) {
     const int first = S.level_ptr[lv + 1], cnt = S.level_ptr[lv + 2] - S.level_ptr[lv + 1];
     if (cnt == 0) continue;
-    mtransfer_down<NT><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
+    if (H.kron)
+      mtransfer_down_kron<NT><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.E1.as<float>(), yh);
+    else
+      mtransfer_down<NT><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
   }
   if (H.prof) {
     e3 = prof_event(H);
@@ -998,8 +1108,13 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
   for (int lv = S.depth - 1; lv >= 0; --lv) {
     const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
     if (cnt == 0) continue;
-    mtransfer_up<1><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv], H.child0.as<int32_t>(),
-                                                H.child1.as<int32_t>(), H.ET.as<float>(), xh);
+    if (H.kron)
+      mtransfer_up_kron<1><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
+                                                       H.child0.as<int32_t>(), H.child1.as<int32_t>(),
+                                                       H.E1.as<float>(), xh);
+    else
+      mtransfer_up<1><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
+                                                  H.child0.as<int32_t>(), H.child1.as<int32_t>(), H.ET.as<float>(), xh);
   }
   if (H.prof) {
     e1 = prof_event(H);
@@ -1021,7 +1136,10 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
   for (int lv = 0; lv < S.depth; ++lv) {
     const int first = S.level_ptr[lv + 1], cnt = S.level_ptr[lv + 2] - S.level_ptr[lv + 1];
     if (cnt == 0) continue;
-    mtransfer_down<1><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
+    if (H.kron)
+      mtransfer_down_kron<1><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.E1.as<float>(), yh);
+    else
+      mtransfer_down<1><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
   }
   if (H.prof) {
     e3 = prof_event(H);

@@ -204,3 +204,22 @@ def test_symmetric_near_field_alone_and_recompressed(case, storage):
         # FP64 oracle's, the bound still holds
         bound = np.sqrt(2.0 * info["discarded"]) * np.linalg.norm(x) + 1e-6 * np.linalg.norm(ref_abs)
         assert np.linalg.norm(yc - ref) <= bound
+
+
+def test_many_columns_on_dense_transfers_after_orthogonalisation():
+    """eps = 0 keeps k' = 64 but replaces the Kronecker-structured transfers by
+    orthonormal dense ones: many columns then run the dense (matrix-core)
+    transfer kernels, and the product is still G~ x."""
+    case = ("sphere", 4, 4, 64)
+    H = oracle(*case)
+    X = np.stack([I.random_vector(H.mesh.n, s, "normal") for s in range(30, 64)], 1)   # 34 columns
+    A = build(case, "f32")
+    try:
+        info = A.recompress(0.0)
+        assert info["rank"] == 64
+        Y = product(A, X)
+    finally:
+        A.close()
+    for j in range(X.shape[1]):
+        ref, scale = H.matvec(X[:, j]), H.matvec(np.abs(X[:, j]))
+        assert np.linalg.norm(Y[:, j] - ref) <= 1e-6 * np.linalg.norm(scale), j
