@@ -153,3 +153,53 @@ def test_regular_rule_far_pair_converges():
     r = np.sqrt(((x[:, None] - y[None]) ** 2).sum(-1))
     ref = mesh.area[0] * mesh.area[1] * np.einsum("a,b,ab->", w, w, 1 / (4 * math.pi * r))
     assert abs(val - ref) < 1e-9 * abs(ref)
+
+
+def _subdivide(P, levels):
+    """Midpoint subdivision of one triangle into 4**levels congruent pieces."""
+    tris = [np.asarray(P, float)]
+    for _ in range(levels):
+        out = []
+        for a, b, c in tris:
+            ab, bc, ca = (a + b) / 2, (b + c) / 2, (c + a) / 2
+            out += [np.array([a, ab, ca]), np.array([ab, b, bc]), np.array([ca, bc, c]), np.array([ab, bc, ca])]
+        tris = out
+    return np.array(tris)
+
+
+def _composite(PA, PB, levels, q=8):
+    """Mean of 1/(4 pi |x - y|) over T_a x T_b: both triangles subdivided, the
+    collapsed Gauss rule of order q (exact to degree 2q - 1) on every sub-pair."""
+    lam, w = Q.collapsed_triangle(q)
+    A, B = _subdivide(PA, levels), _subdivide(PB, levels)
+    X = np.einsum("qk,nkd->nqd", lam, A).reshape(-1, 3)
+    Y = np.einsum("qk,nkd->nqd", lam, B).reshape(-1, 3)
+    wa, wb = np.tile(w, len(A)) / len(A), np.tile(w, len(B)) / len(B)
+    r = np.sqrt(((X[:, None] - Y[None]) ** 2).sum(-1))
+    return wa @ (1.0 / (4.0 * math.pi * r)) @ wb
+
+
+@pytest.mark.parametrize("kind,level", [("sphere", 3), ("cube", 8)])
+def test_regular_rule_on_closest_non_touching_pairs(kind, level):
+    """Accuracy of the regular 7 x 7-point rule where it is weakest: the nearest
+    triangles that share no vertex (the paper fixes the rule, not its error).
+    Reference: the composite high-order rule, converged in the subdivision level
+    (one level vs two agree to 1e-12).  Measured worst relative error: 1.3e-5 on
+    the sphere, 9.4e-5 on the cube (right triangles, closer relative to size)."""
+    import h2_inputs as I
+    V, T = I.mesh_for(kind, level)
+    mesh = Mesh(V, T)
+    nf = NearField(mesh, Kernel())
+    c = mesh.P.mean(1)
+    worst = 0.0
+    for i in (0, 100):
+        touch = set(int(j) for j in mesh.touching(i)) | {i}
+        order = [int(j) for j in np.argsort(np.linalg.norm(c - c[i], axis=1)) if int(j) not in touch]
+        for j in order[:4]:
+            val = nf.regular(np.array([i]), np.array([j]))[0, 0]
+            r1 = mesh.area[i] * mesh.area[j] * _composite(mesh.P[i], mesh.P[j], 1)
+            r2 = mesh.area[i] * mesh.area[j] * _composite(mesh.P[i], mesh.P[j], 2)
+            assert abs(r1 / r2 - 1.0) <= 1e-12, (i, j)
+            worst = max(worst, abs(val / r2 - 1.0))
+    assert worst <= 2e-4
+    assert worst >= 1e-7  # the rule is not exact here: the reference is independent of it
