@@ -70,3 +70,23 @@ def test_degenerate_box_padding():
     for c in flat[:10]:
         t = IP.axis_points(c, 3)
         assert np.isfinite(t).all() and all(np.unique(t[d]).size == 3 for d in range(3))
+
+
+@pytest.mark.parametrize("H,m", [(lambda: sphere(3, 4, 32), 4), (lambda: cube(16, 3, 32), 3)])
+def test_transfer_is_kronecker_product(H, m):
+    """eq. (transfer) with tensor Lagrange polynomials factors per axis:
+    E_c = E_z (x) E_y (x) E_x (x fastest), E_d[i][j] = l_j(xi_i) on axis d.  The
+    one-dimensional factors are built here from the monomial (Vandermonde) form
+    of the Lagrange polynomials, not from the oracle's product formula."""
+    H = H()
+    for c in H.tree.clusters[1:40]:
+        tp, tc = IP.axis_points(c.parent, m), IP.axis_points(c, m)
+        F = []
+        for d in range(3):
+            ctr, half = 0.5 * (tp[d].max() + tp[d].min()), 0.5 * (tp[d].max() - tp[d].min())
+            Vp = np.vander((tp[d] - ctr) / half, m, increasing=True)       # Vp[j][k] = t_j^k
+            Vc = np.vander((tc[d] - ctr) / half, m, increasing=True)
+            F.append(Vc @ np.linalg.inv(Vp))                               # l_j(s_i)
+        K = np.kron(F[2], np.kron(F[1], F[0]))
+        E = H.E(c)
+        assert np.abs(E - K).max() <= 1e-12 * max(1.0, np.abs(E).max()), c.id
