@@ -1,0 +1,37 @@
+"""CPU checks of bench.py's contract that need no GPU: the refusal of more than
+one GPU, the HBM traffic it reads from the committed counter summary, and the
+oracle baseline sampler on a small workload."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and r.stdout == ""
+    assert "one GPU" in r.stderr
+
+
+def test_recorded_traffic_matches_the_algorithmic_bytes():
+    """The counter summary of coupling64 at 1,310,720 triangles: either it was
+    taken on the current kernel source (then its bytes are within 5% above the
+    algorithmic 1,710,034 blocks x 64 x 64 x 4 bytes) or the bench reports none."""
+    t = bench.recorded_traffic("sphere1310k_m4_f32")
+    algorithmic = 1710034 * 64 * 64 * 4.0
+    assert t is None or 1.0 <= t / algorithmic <= 1.05
+    assert bench.recorded_traffic("no_such_workload") is None
+
+
+def test_cpu_baseline_sampler_on_a_small_mesh():
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        out = bench.cpu_baseline_sample("sphere", 4, 4, 64, 2, budget_s=1.0)
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "H2 matvecs/s"
+    assert out["value"] > 0 and abs(out["value"] * out["est_seconds_per_matvec"] - 1.0) < 1e-12
+    assert "subtree" in out["sample"]
