@@ -1,7 +1,9 @@
 // Many right-hand sides: y <- y + alpha G~ X for an n x R block X (FP32 storage,
 // k = 64).  The phases are those of the single-vector product (Algorithms 1-3);
 // with R columns each step becomes a small dense contraction, evaluated on the
-// matrix cores with v_mfma_f32_32x32x2f32.
+// matrix cores with v_mfma_f32_32x32x2f32 -- except the transfers of handles with
+// Kronecker factors, which apply the three 4 x 4 factors per column in registers
+// (12 multiply-adds per coefficient instead of 64).
 //
 // Internal layouts (RP = 32 or 64 right-hand sides per pass, zero-padded):
 //   x_c, y_c   [n][RP]        position-major, right-hand sides contiguous
