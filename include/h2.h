@@ -217,11 +217,13 @@ int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* inf
  * library's, not the paper's).  One knob decides the tiles of the path a call
  * takes; several values compute the same product with different tiles (and a
  * different summation order, within the storage precision):
- *   H2_TUNE_PASS_COLUMNS  many right-hand sides (nrhs >= 2) with real kernels,
- *                         H2_F32 storage, k = 64, full storage: right-hand sides
- *                         per pass, 32 (one 32x32 MFMA column tile per wave in the
- *                         coupling, two 16-column near-field tiles) or 64 (two and
- *                         four).  Built-in rule: 32 if nrhs <= 32, else 64.
+ *   H2_TUNE_PASS_COLUMNS  many right-hand sides (nrhs >= 2) on the matrix-core
+ *                         path: real kernels, H2_F32 storage, k = 64, leaves of
+ *                         at most 64 triangles, no symmetric storage, S stored
+ *                         or on the fly.  Right-hand sides per pass: 32 (one
+ *                         32x32 MFMA column tile per wave in the coupling, two
+ *                         16-column near-field tiles) or 64 (two and four).
+ *                         Built-in rule: 32 if nrhs <= 32, else 64.
  *   H2_TUNE_SMALL_SLOT    single-vector coupling with k <= 32 (recompressed
  *                         bases): lanes per block-row slot of a wave, 16 (four
  *                         blocks of a row cluster at a time, needs k <= 16) or 32
