@@ -35,3 +35,24 @@ def test_cpu_baseline_sampler_on_a_small_mesh():
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "H2 matvecs/s"
     assert out["value"] > 0 and abs(out["value"] * out["est_seconds_per_matvec"] - 1.0) < 1e-12
     assert "subtree" in out["sample"]
+
+
+def test_profile_commands_run_committed_files_with_known_flags():
+    """Every rocprofv3 command quoted in profiles/ runs bench.py from the
+    repository with options bench.py still accepts."""
+    import re
+    import subprocess
+    helptext = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True,
+                              text=True, timeout=120).stdout
+    prof = os.path.join(ROOT, "profiles")
+    names = sorted(os.listdir(prof))
+    assert names
+    for name in names:
+        text = open(os.path.join(prof, name)).read()
+        cmds = [ln for ln in text.splitlines() if ln.strip().startswith("timeout") and "rocprofv3" in ln]
+        assert cmds, name
+        for c in cmds:
+            prog = c.split(" -- ", 1)[1].split()
+            assert prog[0] == "python3" and prog[1] == "$R/bench.py", (name, c)
+            for flag in re.findall(r"(--[a-z][a-z0-9-]*)", " ".join(prog[2:])):
+                assert flag in helptext, (name, flag)
