@@ -156,12 +156,14 @@ def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
     dtypes = {torch.float64: H2_R64, torch.float32: H2_R32, torch.complex128: H2_C128, torch.complex64: H2_C64}
     if x.dtype != y.dtype or x.dtype not in dtypes:
         raise TypeError("x and y must have the same dtype: float64, float32, complex128 or complex64")
-    if not (x.is_cuda and y.is_cuda):
-        raise TypeError("x and y must be device tensors")
+    if x.dim() not in (1, 2) or x.shape != y.shape:
+        raise ValueError("x and y must have the same shape, n or n x nrhs")
     nrhs = 1 if x.dim() == 1 else x.shape[1]
     n = x.shape[0]
-    if x.shape != y.shape:
-        raise ValueError("x and y must have the same shape")
+    if n != h2_info(h)["n"]:
+        raise ValueError("x has %d rows, the matrix has %d" % (n, h2_info(h)["n"]))
+    if not (x.is_cuda and y.is_cuda):
+        raise TypeError("x and y must be device tensors")
     # a single column may carry any stride in its second dimension
     ldx = x.stride(1) if x.dim() == 2 and nrhs > 1 else n
     ldy = y.stride(1) if y.dim() == 2 and nrhs > 1 else n
@@ -179,8 +181,16 @@ def h2_solve(h, b, z, method="cg", rtol=1e-8, maxit=1000, restart=50, refine=Fal
     the initial guess and the result."""
     import torch
     want = torch.complex128 if b.is_complex() else torch.float64
-    if b.dtype != want or z.dtype != want or not (b.is_cuda and z.is_cuda):
-        raise TypeError("b and z must be float64 (complex128 for Helmholtz) device tensors")
+    if b.dtype != want or z.dtype != want:
+        raise TypeError("b and z must be float64 (complex128 for Helmholtz) tensors")
+    n = h2_info(h)["n"]
+    for nm, v in (("b", b), ("z", z)):
+        if not (v.dim() == 1 or (v.dim() == 2 and v.shape[1] == 1)) or v.shape[0] != n:
+            raise ValueError("%s must have shape (n,) or (n, 1) with n = %d, got %s" % (nm, n, tuple(v.shape)))
+        if not v.is_contiguous():
+            raise ValueError("%s must be contiguous" % nm)
+    if not (b.is_cuda and z.is_cuda):
+        raise TypeError("b and z must be device tensors")
     p = h2_solve_params(H2_CG if method == "cg" else H2_GMRES, int(restart), int(maxit), float(rtol),
                         1 if refine else 0, float(inner_rtol))
     info = h2_solve_info()

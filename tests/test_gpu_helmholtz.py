@@ -13,6 +13,7 @@ import pytest
 import h2_inputs as I
 from oracle.h2 import H2Oracle
 from oracle.kernels import HELMHOLTZ, LAPLACE, Kernel
+from tests import bounds
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -62,11 +63,15 @@ def test_helmholtz_matvec_matches_oracle(case, storage):
                 assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
             else:
                 assert np.linalg.norm(y - ref) <= 1e-6 * np.linalg.norm(scale)
+                bounds.check(y, ref, scale, "f32", "Helmholtz %s %s %s" % (case, storage + ("_otf" if otf else ""),
+                                                                           dt))
         if storage == "f32":
             xd = torch.tensor(x, dtype=torch.complex128, device="cuda")
             yd = torch.zeros_like(xd)
             A.matvec(xd, yd, acc64=True)
-            assert np.linalg.norm(yd.cpu().numpy() - ref) <= 1e-6 * np.linalg.norm(scale)
+            y64 = yd.cpu().numpy()
+            assert np.linalg.norm(y64 - ref) <= 1e-6 * np.linalg.norm(scale)
+            bounds.check(y64, ref, scale, "f32", "Helmholtz acc64 %s otf=%d" % (case, otf))
         # real vectors are rejected for a complex matrix
         with pytest.raises(h2.H2Error):
             A.matvec(torch.zeros(H.mesh.n, dtype=torch.float64, device="cuda"))
@@ -152,9 +157,12 @@ def test_helmholtz_multi_rhs(case, nrhs, otf):
     finally:
         A.close()
     for j in range(nrhs):
-        ref = Y0[:, j] - 0.5 * H.matvec(X[:, j])
+        gx = H.matvec(X[:, j])
+        ref = Y0[:, j] - 0.5 * gx
         scale = 0.5 * L.matvec(np.abs(X[:, j]))
         assert np.linalg.norm(Y[:, j] - ref) <= 1e-6 * np.linalg.norm(scale), j
+        bounds.check(Y[:, j] - Y0[:, j], -0.5 * gx, scale, "f32", "Helmholtz multi %s R=%d otf=%d col %d"
+                     % (case, nrhs, otf, j), extra=4.5e-16 * np.abs(Y0[:, j]))
 
 
 def test_helmholtz_otf_full_size_sphere327k():
@@ -185,10 +193,15 @@ def test_helmholtz_otf_full_size_sphere327k():
         ad = torch.tensor(np.abs(X).T.copy(), device="cuda").t()
         sc = torch.zeros_like(ad)
         Lp.matvec(ad, sc)
-        scale = np.linalg.norm(sc.cpu().numpy(), axis=0)
+        SC = sc.cpu().numpy()
+        scale = np.linalg.norm(SC, axis=0)
     finally:
         Lp.close()
     (Ys, y1s), (Yo, y1o) = out[False], out[True]
     assert np.linalg.norm(y1o - y1s) <= 2e-6 * scale[0]
+    # both products carry FP32 errors: twice the bounds of one
+    bounds.check(y1o, y1s, 2 * SC[:, 0], "f32", "Helmholtz 327k otf vs stored, one column", t_rel=1e-5)
     for j in range(16):
         assert np.linalg.norm(Yo[:, j] - Ys[:, j]) <= 2e-6 * scale[j], j
+        bounds.check(Yo[:, j], Ys[:, j], 2 * SC[:, j], "f32", "Helmholtz 327k otf vs stored col %d" % j,
+                     t_rel=1e-5)

@@ -9,7 +9,9 @@ Tolerances (2-norm over the compared entries):
                   the sums over all n columns cancel by a factor of order sqrt(n),
                   so the scale is G~ applied to |x|, not G~ x)
   BF16 coupling   ||y - y_ref|| <= 2e-3  ||G~ |x| ||   (BF16 unit roundoff 2e-3)
-The same bounds hold with FP64 accumulation over FP32/BF16 storage.
+The same bounds hold with FP64 accumulation over FP32/BF16 storage.  Every
+FP32/BF16 comparison also holds the product to a bound relative to ||G~ x|| and
+entry by entry to a multiple of u (G~ |x|)_i (tests/bounds.py).
 """
 import functools
 
@@ -19,6 +21,7 @@ import pytest
 import h2_inputs as I
 from oracle.h2 import H2Oracle
 from oracle.kernels import Kernel
+from tests import bounds
 from tests.closed_forms import poly_kernel_product
 
 torch = pytest.importorskip("torch")
@@ -68,8 +71,10 @@ def test_matvec_matches_oracle(case, storage):
         y = gpu_matvec(A, x)
         assert err(storage, y, ref, ref_abs) <= TOL[storage]
         if storage != "f64":
+            bounds.check(y, ref, ref_abs, storage, "matvec %s" % (case,))
             y64 = gpu_matvec(A, x, acc64=True)
             assert err(storage, y64, ref, ref_abs) <= TOL[storage]
+            bounds.check(y64, ref, ref_abs, storage, "matvec acc64 %s" % (case,))
     finally:
         A.close()
 
@@ -114,6 +119,7 @@ def test_accumulate_alpha_and_float32_vectors():
         assert rel(y, ref) <= 1e-12
         y32 = gpu_matvec(A, x, dtype=torch.float32)
         assert rel(y32, H.matvec(x), H.matvec(np.abs(x))) <= 1e-6
+        bounds.check(y32, H.matvec(x), H.matvec(np.abs(x)), "f32", "float32 vectors")
     finally:
         A.close()
 
@@ -159,9 +165,12 @@ def test_empty_nrhs_and_bad_arguments():
         x = torch.zeros(T.shape[0], 0, dtype=torch.float64, device="cuda")
         assert h2.lib().h2_matvec(A.h, 0, 0, x.data_ptr(), T.shape[0], x.data_ptr(), T.shape[0], 1.0, 0,
                                   None) == 0
-        with pytest.raises(h2.H2Error):
+        with pytest.raises(ValueError):             # the binding checks the length
             h2.h2_matvec(A.h, torch.zeros(5, dtype=torch.float64, device="cuda"),
                          torch.zeros(5, dtype=torch.float64, device="cuda"))
+        v5 = torch.zeros(5, dtype=torch.float64, device="cuda")
+        assert h2.lib().h2_matvec(A.h, 1, 0, v5.data_ptr(), 5, v5.data_ptr(), 5, 1.0, 0,
+                                  None) == h2.H2_EINVAL     # the C ABI rejects ld < n
         assert h2.lib().h2_matvec(A.h, 1, 7, x.data_ptr(), T.shape[0], x.data_ptr(), T.shape[0], 1.0, 0,
                                   None) == h2.H2_EINVAL
     finally:
@@ -208,9 +217,14 @@ def test_multi_rhs_matches_oracle(case, nrhs, otf):
     finally:
         A.close()
     for j in range(nrhs):
-        ref = Y0[:, j] + 0.5 * H.matvec(X[:, j])
+        gx = H.matvec(X[:, j])
+        ref = Y0[:, j] + 0.5 * gx
         scale = 0.5 * H.matvec(np.abs(X[:, j]))
         assert np.linalg.norm(Y[:, j] - ref) <= 1e-6 * np.linalg.norm(scale), j
+        # Y0 ~ N(0,1) is larger than G~x: the FP64 rounding of the sum enters
+        d = Y[:, j] - Y0[:, j]
+        bounds.check(d, 0.5 * gx, scale, "f32", "multi-RHS %s R=%d otf=%d col %d" % (case, nrhs, otf, j),
+                     extra=4.5e-16 * np.abs(Y0[:, j]))
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -230,7 +244,10 @@ def test_on_the_fly_coupling_matches_oracle(case, storage):
         y = gpu_matvec(A, x)
         assert err(storage, y, ref, ref_abs) <= TOL[storage]
         if storage == "f32":
-            assert err(storage, gpu_matvec(A, x, acc64=True), ref, ref_abs) <= TOL[storage]
+            bounds.check(y, ref, ref_abs, storage, "on-the-fly S %s" % (case,))
+            y64 = gpu_matvec(A, x, acc64=True)
+            assert err(storage, y64, ref, ref_abs) <= TOL[storage]
+            bounds.check(y64, ref, ref_abs, storage, "on-the-fly S acc64 %s" % (case,))
         with pytest.raises(h2.H2Error):
             A.export(h2.H2_X_S, 0)
     finally:
@@ -276,7 +293,10 @@ def test_symmetric_storage_matches_oracle(case, storage, otf):
         scale = np.linalg.norm(ref if storage == "f64" else ref_abs)
         assert np.linalg.norm(ya - (y0 - 0.5 * ref)) <= 0.5 * TOL[storage] * scale + 4e-16 * np.linalg.norm(y0)
         if storage == "f32":
-            assert err(storage, gpu_matvec(A, x, acc64=True), ref, ref_abs) <= TOL[storage]
+            bounds.check(y, ref, ref_abs, storage, "symmetric %s otf=%d" % (case, otf))
+            y64 = gpu_matvec(A, x, acc64=True)
+            assert err(storage, y64, ref, ref_abs) <= TOL[storage]
+            bounds.check(y64, ref, ref_abs, storage, "symmetric acc64 %s otf=%d" % (case, otf))
         X = np.asfortranarray(np.stack([x, y0], axis=1))
         xd = torch.tensor(X, device="cuda").t().contiguous().t()
         yd = torch.zeros_like(xd)

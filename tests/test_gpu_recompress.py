@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import h2_inputs as I
+from tests import bounds
 from oracle.h2 import H2Oracle
 from oracle.kernels import Kernel
 from oracle.recompress import Recompressed
@@ -196,6 +197,8 @@ def test_symmetric_near_field_alone_and_recompressed(case, storage):
     tol = 1e-12 if storage == "f64" else 1e-6
     scale = np.linalg.norm(ref) if storage == "f64" else np.linalg.norm(ref_abs)
     assert np.linalg.norm(y - ref) <= tol * scale
+    if storage == "f32":
+        bounds.check(y, ref, ref_abs, "f32", "symmetric near field %s" % (case,))
     if storage == "f64":
         assert info["rank"] == padded(O.max_rank, H.k)
         assert np.linalg.norm(yc - ref_c) <= 1e-10 * np.linalg.norm(ref_c)
@@ -223,3 +226,4 @@ def test_many_columns_on_dense_transfers_after_orthogonalisation():
     for j in range(X.shape[1]):
         ref, scale = H.matvec(X[:, j]), H.matvec(np.abs(X[:, j]))
         assert np.linalg.norm(Y[:, j] - ref) <= 1e-6 * np.linalg.norm(scale), j
+        bounds.check(Y[:, j], ref, scale, "f32", "dense transfers after orthogonalisation col %d" % j)

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import h2_inputs as I
+from tests import bounds
 from oracle.h2 import H2Oracle
 from oracle.kernels import Kernel
 from oracle.recompress import Recompressed
@@ -60,6 +61,7 @@ def test_pass_columns_every_value_matches_oracle(nrhs):
     for v, Y in list(out.items()) + [("tuned", yt)]:
         for j in range(nrhs):
             assert np.linalg.norm(Y[:, j] - ref[:, j]) <= 1e-6 * np.linalg.norm(scale[:, j]), (v, j)
+            bounds.check(Y[:, j], ref[:, j], scale[:, j], "f32", "pass columns %s, R=%d col %d" % (v, nrhs, j))
     assert np.array_equal(out[0], out[32 if nrhs <= 32 else 64])      # the built-in rule
     assert info["knob"] == "pass_columns" and info["values"] == [32, 64]
     assert all(t > 0 for t in info["ms"]) and info["chosen"] in (32, 64)

@@ -197,3 +197,32 @@ def test_symmetric_near_field_only():
         args.update(kw)
         with pytest.raises(h2.H2Error):
             h2.h2_free(h2.build_h2(V, T, **args))
+
+
+def test_wrapper_rejects_bad_vector_shapes():
+    """The binding checks vector shapes against the matrix before any launch: the
+    C ABI takes no vector length, so a short vector would be read out of bounds."""
+    import torch
+    V, T = I.icosphere(1)
+    h = h2.build_h2(V, T, order=2, leaf=8, host_only=True)
+    try:
+        n = h2.h2_info(h)["n"]
+        ok = torch.zeros(n, dtype=torch.float64)
+        for x, y in ((torch.zeros(n - 1, dtype=torch.float64), torch.zeros(n - 1, dtype=torch.float64)),
+                     (torch.zeros(n + 3, 2, dtype=torch.float64), torch.zeros(n + 3, 2, dtype=torch.float64)),
+                     (ok, torch.zeros(n, 1, dtype=torch.float64)),
+                     (torch.zeros(2, n, 1, dtype=torch.float64), torch.zeros(2, n, 1, dtype=torch.float64))):
+            with pytest.raises(ValueError):
+                h2.h2_matvec(h, x, y)
+        with pytest.raises(TypeError):                         # right shape, but host memory
+            h2.h2_matvec(h, ok, ok.clone())
+        for b in (torch.zeros(n - 1, dtype=torch.float64), torch.zeros(n, 2, dtype=torch.float64),
+                  torch.zeros(2 * n, dtype=torch.float64)[::2]):
+            with pytest.raises(ValueError):
+                h2.h2_solve(h, b, torch.zeros(n, dtype=torch.float64))
+            with pytest.raises(ValueError):
+                h2.h2_solve(h, torch.zeros(n, dtype=torch.float64), b.clone() if b.is_contiguous() else b)
+        with pytest.raises(TypeError):
+            h2.h2_solve(h, ok, ok.clone())
+    finally:
+        h2.h2_free(h)

@@ -95,3 +95,49 @@ def test_eta_controls_block_count():
     a = sphere(3, 3, 32, 0.5)
     b = sphere(3, 3, 32, 1.0)
     assert len(b.adm) + len(b.inadm) < len(a.adm) + len(a.inadm)
+
+
+def _box(lo, hi):
+    from oracle.cluster import Cluster
+    c = Cluster()
+    c.lo, c.hi = np.array(lo, dtype=np.float64), np.array(hi, dtype=np.float64)
+    return c
+
+
+def test_diam_is_box_diagonal():
+    """diam tau is the Euclidean length of the box diagonal, not its longest side:
+    the box [0,1]x[0,2]x[0,2] has diagonal sqrt(1+4+4) = 3 and longest side 2."""
+    assert _box([0, 0, 0], [1, 2, 2]).diam() == 3.0
+    assert _box([-1, 5, 2], [1, 8, 8]).diam() == 7.0            # sqrt(4 + 9 + 36)
+    assert _box([0.25, 0.25, 0.25], [0.25, 0.25, 0.25]).diam() == 0.0
+
+
+def test_admissibility_boundary_hand_built_boxes():
+    """eq. (admissibility) with eta = 1/2 reads max(diam) <= dist.  Two boxes of
+    diagonal 3 separated along x by a gap g have dist = g: admissible at g = 3
+    (the boundary, equality allowed), not at g = 3 - 2^-40 just across it, and
+    not at g = 2.5 (a longest-side diameter, 2, would wrongly accept it); with
+    eta = 1 the condition is max(diam) <= 2 dist, so g = 1.5 is the boundary.
+    Writing eta for 2 eta, or the longest side for the diagonal, fails a case."""
+    A = _box([0, 0, 0], [1, 2, 2])
+    for gap, eta, want in ((3.0, 0.5, True), (3.0 - 2.0 ** -40, 0.5, False), (2.5, 0.5, False),
+                           (4.0, 0.5, True), (1.5, 1.0, True), (1.5 - 2.0 ** -40, 1.0, False),
+                           (3.0, 0.25, False), (6.0, 0.25, True)):
+        B = _box([1 + gap, 0, 0], [2 + gap, 2, 2])
+        assert box_dist(A, B) == gap and box_dist(B, A) == gap
+        assert admissible(A, B, eta) is want, (gap, eta)
+        assert admissible(B, A, eta) is want, (gap, eta)
+    # gaps in two axes: dist = sqrt(3^2 + 4^2) = 5
+    B = _box([4, 6, 0], [5, 8, 2])
+    assert box_dist(A, B) == 5.0
+    assert admissible(A, B, 0.5) and not admissible(A, B, 0.25)   # 3 <= 5, 3 > 2.5
+    # intersecting or touching boxes have dist 0 and are never admissible
+    for lo in ([0.5, 1, 1], [1, 0, 0], [1, 2, 2]):
+        B = _box(lo, np.add(lo, [1, 2, 2]))
+        assert box_dist(A, B) == 0.0 and not admissible(A, B, 1e6)
+    # the larger of the two diameters decides
+    small = _box([10, 0, 0], [10.5, 0.5, 0.5])                   # diam sqrt(0.75) < 3
+    assert box_dist(A, small) == 9.0
+    assert admissible(A, small, 0.5)
+    big = _box([4, 0, 0], [14, 0, 0])                              # diam 10 > dist 3
+    assert not admissible(A, big, 0.5) and admissible(A, big, 10.0 / 6.0)
