@@ -385,7 +385,7 @@ def bench_serve(args):
     t0 = time.perf_counter()
     for name in meshes:                       # structures are built once and stay resident
         for kern, kap in kernels:
-            S._make_resident((name, kern, float(kap)), 0)
+            S._make_resident((name, kern, float(kap)))
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     log("serve: %d structures resident, %.1f GB, built in %.1f s" % (len(S.resident), S.used_bytes() / 1e9, build_s))

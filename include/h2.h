@@ -66,7 +66,9 @@ extern "C" {
 /* storage precision of V, E, S and the near field */
 #define H2_F64 0       /* everything FP64 */
 #define H2_F32 1       /* everything FP32 */
-#define H2_F32_SBF16 2 /* coupling matrices BF16, the rest FP32 */
+#define H2_F32_SBF16 2 /* coupling matrices BF16, the rest FP32; S is also kept in FP32
+                          for the products with H2_ACC_F64 (the outer residual of iterative
+                          refinement), so BF16 S only ever serves the inner solves */
 
 /* element type of user vectors */
 #define H2_R64 0  /* double */
@@ -75,7 +77,9 @@ extern "C" {
 #define H2_C64 3  /* complex float, interleaved (re, im); Helmholtz only */
 
 /* h2_matvec flags */
-#define H2_ACC_F64 1 /* accumulate in FP64 even when the matrix is stored in FP32/BF16 */
+#define H2_ACC_F64 1 /* accumulate in FP64 even when the matrix is stored in FP32/BF16;
+                        with H2_F32_SBF16 storage the product applies the FP32 copy of S */
+#define H2_OVERWRITE 2 /* assign y <- alpha G~ x instead of accumulating (y is not read) */
 
 /* h2_params.flags */
 #define H2_HOST_ONLY 1   /* build only the trees (no device work); for structure inspection */
@@ -139,7 +143,8 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out);
 
 /* y <- y + alpha G~ x for nrhs columns.  dtype: H2_R64 or H2_R32 for real
  * kernels, H2_C128 or H2_C64 (interleaved complex, ld counted in complex
- * elements) for the Helmholtz kernel; alpha is real.  flags: 0 or H2_ACC_F64.
+ * elements) for the Helmholtz kernel; alpha is real.  flags: 0 or any of
+ * H2_ACC_F64, H2_OVERWRITE.
  * Asynchronous on `stream`. */
 int h2_matvec(h2_handle h, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
               double alpha, int flags, void* stream);
@@ -149,29 +154,87 @@ int h2_matvec(h2_handle h, int nrhs, int dtype, const void* x, int64_t ldx, void
 #define H2_GMRES 1
 typedef struct {
   int method;        /* H2_CG (Laplace: G~ symmetric positive definite) or H2_GMRES */
-  int restart;       /* GMRES restart length                                         */
+  int restart;       /* GMRES restart length, 1..120                                */
   int maxit;         /* maximum number of inner iterations in total                 */
-  double rtol;       /* stop when ||b - G~ z|| <= rtol ||b||                        */
+  double rtol;       /* stop when ||b_j - G~ z_j|| <= rtol ||b_j|| for every column j */
   int refine;        /* 0: plain solve with the matrix's own accumulation;
-                        1: FP64 iterative refinement -- outer residuals with FP64
-                           accumulation, inner solves with storage-precision
+                        1: FP64 iterative refinement -- outer residuals from products
+                           with H2_ACC_F64 (FP64 accumulation; with H2_F32_SBF16 the
+                           FP32 copy of S), inner solves with the storage precision's
                            accumulation to inner_rtol                              */
-  double inner_rtol; /* inner tolerance of the refinement                          */
+  double inner_rtol; /* inner tolerance of the refinement, in (0, 1)               */
 } h2_solve_params;
 
 typedef struct {
-  int iterations;       /* total inner iterations                          */
-  int outer;            /* refinement steps (1 without refinement)         */
-  double rel_residual;  /* ||b - G~ z|| / ||b|| recomputed at the end, FP64 */
-  double seconds;       /* wall time                                        */
+  int iterations;       /* total inner iterations (one product each)          */
+  int outer;            /* inner solves started (refinement steps)            */
+  double rel_residual;  /* max over columns of ||b - G~ z|| / ||b||, FP64,
+                           from the last outer residual                      */
+  double seconds;       /* wall time                                          */
 } h2_solve_info;
 
-/* Solves G~ z = b for one right-hand side (device vectors: FP64 for real
- * kernels, interleaved complex FP64 for Helmholtz, which requires H2_GMRES).
- * z is both the initial guess and the result.  Returns H2_ENOTCONV if rtol was
- * not met (z and info are still written). */
-int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p,
-             h2_solve_info* info, void* stream);
+/* Solves G~ Z = B for nrhs columns at once (device blocks, column-major,
+ * leading dimensions ldb, ldz >= n; dtype H2_R64 for real kernels, H2_C128 for
+ * Helmholtz, which requires H2_GMRES).  Z is both the initial guess and the
+ * result.  Every iteration applies one product to all columns (the many-
+ * right-hand-side path when nrhs >= 2); inner products, the GMRES Hessenberg
+ * columns, Givens rotations and triangular solves are FP64 on the device; the
+ * host reads one residual per column and iteration.  The handle keeps the
+ * solver's workspace (about (5 + restart) n nrhs FP64 values) for later calls.
+ * Returns H2_ENOTCONV if some column missed rtol (Z and info still written),
+ * also when a non-finite value appeared (h2_last_error says which). */
+int h2_solve(h2_handle h, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+             const h2_solve_params* p, h2_solve_info* info, void* stream);
+
+/* Step-wise form of the same solver, for callers that batch the products of
+ * several solves (the solve service issues one many-right-hand-side product
+ * per matrix for all the solves that wait on it).  The solver never touches a
+ * matrix: it writes the block X whose product it needs and consumes Y = G~ X.
+ *   h2_krylov_workspace  device bytes a solve of nrhs columns of length n needs
+ *                        (-1 for invalid arguments)
+ *   h2_krylov_create     a solver on caller-owned DEVICE memory `workspace`
+ *                        (256-byte aligned, >= the bytes above, kept until
+ *                        destroy) and optional caller-owned PINNED host memory
+ *                        `host_status` of 3 nrhs doubles (NULL: the solver
+ *                        allocates its own); allocates no device memory
+ *   h2_krylov_begin      starts a solve of G~ Z = B; b must stay valid and
+ *                        unchanged until the solve ends; z0 = NULL means Z = 0
+ *   h2_krylov_next       returns H2_KS_PRODUCT and writes the block X (n x nrhs,
+ *                        ldx) whose product is needed, with the h2_matvec flags
+ *                        it needs in *flags (H2_ACC_F64 for the outer residual
+ *                        of a refinement); or returns the final state.  With
+ *                        x = NULL it only reports the state and the flags (no
+ *                        device work), so a caller can group solves by flags
+ *   h2_krylov_advance    consumes Y = G~ X (ldy), computed with those flags
+ *   h2_krylov_poll       after the stream has completed the advance: takes the
+ *                        control decisions and returns the state; st may be NULL
+ *   h2_krylov_residuals  relative outer residual per column (host copy, nrhs)
+ *   h2_krylov_solution   copies Z into z (ldz)
+ * next, advance and solution are asynchronous on `stream`; one solver must stay
+ * on one stream.  Calls return a negative H2_E* code on invalid use. */
+#define H2_KS_PRODUCT 1  /* the solve needs another product                  */
+#define H2_KS_DONE 2     /* every column met rtol                             */
+#define H2_KS_NOTCONV 3  /* maxit or the refinement steps ran out             */
+#define H2_KS_FAILED 4   /* a non-finite value appeared; see message          */
+typedef struct h2_krylov_s* h2_krylov;
+typedef struct {
+  int state;
+  int iterations;
+  int outer;
+  int products;
+  double rel_residual; /* max over columns of the latest relative residual   */
+  char message[128];
+} h2_krylov_status;
+int64_t h2_krylov_workspace(int dtype, int64_t n, int nrhs, const h2_solve_params* p);
+int h2_krylov_create(int dtype, int64_t n, int nrhs, const h2_solve_params* p, void* workspace, int64_t bytes,
+                     double* host_status, h2_krylov* out);
+int h2_krylov_begin(h2_krylov k, const void* b, int64_t ldb, const void* z0, int64_t ldz, void* stream);
+int h2_krylov_next(h2_krylov k, void* x, int64_t ldx, int* flags, void* stream);
+int h2_krylov_advance(h2_krylov k, const void* y, int64_t ldy, void* stream);
+int h2_krylov_poll(h2_krylov k, h2_krylov_status* st);
+int h2_krylov_residuals(h2_krylov k, double* out);
+int h2_krylov_solution(h2_krylov k, void* z, int64_t ldz, void* stream);
+void h2_krylov_destroy(h2_krylov k);
 
 /* Algebraic recompression (a smaller-rank H^2 matrix of the same block
  * structure; the paper names such approximations as future work: the GCA-H^2

@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("H2_OFFLOAD_ARCH", "gfx950")
 
 HOST_SOURCES = ["structure.cpp", "quadrules.cpp"]
-HIP_SOURCES = ["assemble.hip", "matvec.hip", "matvec_multi.hip", "solve.hip", "krylov.hip", "recompress.hip",
+HIP_SOURCES = ["assemble.hip", "matvec.hip", "matvec_multi.hip", "ksolve.hip", "krylov.hip", "recompress.hip",
                "tune.hip", "capi.hip"]
 
 

@@ -12,6 +12,8 @@
 // the x-triangle, so g_ij and g_ji are computed identically.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -443,6 +445,14 @@ void assemble_typed(h2_handle_s& H) {
                                                                    H.adm_col.as<int32_t>(), H.pts.as<double>(),
                                                                    H.Smat.as<SST>());
     H2_HIP(hipGetLastError());
+    if constexpr (std::is_same<SST, bf16>::value) {
+      // the same entries rounded to FP32, for the FP64-accumulated products
+      H.Smat32.alloc(static_cast<size_t>(nadm) * kk * sizeof(float));
+      asm_coupling<float, false><<<static_cast<unsigned>(nadm), 256>>>(nadm, k, m, kf, arow.as<int32_t>(),
+                                                                      H.adm_col.as<int32_t>(), H.pts.as<double>(),
+                                                                      H.Smat32.as<float>());
+      H2_HIP(hipGetLastError());
+    }
   }
 
   // near field: block row / first column of every inadmissible block

@@ -4,11 +4,13 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
 
 #include "handle.h"
+#include "ksolve.h"
 
 namespace {
 thread_local std::string g_err;
@@ -35,6 +37,7 @@ int guarded(F&& f) {
 }  // namespace
 
 h2_handle_s::~h2_handle_s() {
+  if (kstat) (void)hipHostFree(kstat);
   std::vector<hipEvent_t> all(events);
   for (auto& pe : pending) {
     all.push_back(pe.second.first);
@@ -185,15 +188,103 @@ int h2_matvec(h2_handle h, int nrhs, int dtype, const void* x, int64_t ldx, void
   });
 }
 
-int h2_solve(h2_handle h, const void* b, void* z, const h2_solve_params* p, h2_solve_info* info,
-             void* stream) {
+int h2_solve(h2_handle h, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+             const h2_solve_params* p, h2_solve_info* info, void* stream) {
   return guarded([&]() -> int {
-    if (!h || !b || !z || !p) return fail(H2_EINVAL, "NULL argument");
+    if (!h || !p) return fail(H2_EINVAL, "NULL argument");
     h2_solve_info tmp{};
-    const int rc = h2::solve(*h, b, z, *p, info ? *info : tmp, static_cast<hipStream_t>(stream));
+    const int rc = h2::solve_multi(*h, nrhs, dtype, b, ldb, z, ldz, *p, info ? *info : tmp,
+                                   static_cast<hipStream_t>(stream));
     if (rc == H2_ENOTCONV) return fail(rc, "solver did not reach the tolerance");
     return rc;
   });
+}
+
+int64_t h2_krylov_workspace(int dtype, int64_t n, int nrhs, const h2_solve_params* p) {
+  try {
+    if (!p || n < 1 || nrhs < 1 || (dtype != H2_R64 && dtype != H2_C128)) return -1;
+    h2::KSolver::check_params(*p, dtype == H2_C128);
+    return static_cast<int64_t>(h2::klayout(dtype, n, nrhs, *p).bytes);
+  } catch (...) {
+    return -1;
+  }
+}
+
+int h2_krylov_create(int dtype, int64_t n, int nrhs, const h2_solve_params* p, void* workspace, int64_t bytes,
+                     double* host_status, h2_krylov* out) {
+  return guarded([&]() -> int {
+    if (!p || !out) return fail(H2_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (bytes < 0) return fail(H2_EINVAL, "negative workspace size");
+    *out = reinterpret_cast<h2_krylov>(
+        new h2::KSolver(dtype, n, nrhs, *p, workspace, static_cast<size_t>(bytes), host_status));
+    return H2_OK;
+  });
+}
+
+static h2::KSolver* ks(h2_krylov k) { return reinterpret_cast<h2::KSolver*>(k); }
+
+int h2_krylov_begin(h2_krylov k, const void* b, int64_t ldb, const void* z0, int64_t ldz, void* stream) {
+  return guarded([&]() -> int {
+    if (!k) return fail(H2_EINVAL, "NULL solver");
+    ks(k)->begin(b, ldb, z0, ldz, static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
+int h2_krylov_next(h2_krylov k, void* x, int64_t ldx, int* flags, void* stream) {
+  return guarded([&]() -> int {
+    if (!k) return fail(H2_EINVAL, "NULL solver");
+    return ks(k)->next(x, ldx, flags, static_cast<hipStream_t>(stream));
+  });
+}
+
+int h2_krylov_advance(h2_krylov k, const void* y, int64_t ldy, void* stream) {
+  return guarded([&]() -> int {
+    if (!k) return fail(H2_EINVAL, "NULL solver");
+    ks(k)->advance(y, ldy, static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
+int h2_krylov_poll(h2_krylov k, h2_krylov_status* st) {
+  return guarded([&]() -> int {
+    if (!k) return fail(H2_EINVAL, "NULL solver");
+    h2::KSolver& K = *ks(k);
+    const int s = K.poll();
+    if (st) {
+      st->state = s;
+      st->iterations = K.iterations;
+      st->outer = K.outer;
+      st->products = K.products;
+      st->rel_residual = K.last_rel;
+      std::snprintf(st->message, sizeof(st->message), "%s", K.message.c_str());
+    }
+    return s;
+  });
+}
+
+int h2_krylov_residuals(h2_krylov k, double* out) {
+  return guarded([&]() -> int {
+    if (!k || !out) return fail(H2_EINVAL, "NULL argument");
+    ks(k)->residuals(out);
+    return H2_OK;
+  });
+}
+
+int h2_krylov_solution(h2_krylov k, void* z, int64_t ldz, void* stream) {
+  return guarded([&]() -> int {
+    if (!k) return fail(H2_EINVAL, "NULL solver");
+    ks(k)->solution(z, ldz, static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
+void h2_krylov_destroy(h2_krylov k) {
+  try {
+    delete ks(k);
+  } catch (...) {
+  }
 }
 
 int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* info, void* stream) {
@@ -240,7 +331,7 @@ int h2_info(h2_handle h, h2_stats* out) {
     out->k = S.k;
     out->storage = h->P.storage;
     out->kernel = h->P.kernel;
-    out->bytes_S = static_cast<int64_t>(h->Smat.bytes);
+    out->bytes_S = static_cast<int64_t>(h->Smat.bytes + h->Smat32.bytes);
     out->bytes_N = static_cast<int64_t>(h->Nmat.bytes);
     out->bytes_V = static_cast<int64_t>(h->Vf.bytes + h->Vb.bytes);
     out->bytes_E = static_cast<int64_t>(h->F.bytes + h->ET.bytes + h->E1.bytes);

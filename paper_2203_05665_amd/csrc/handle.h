@@ -78,6 +78,9 @@ struct h2_handle_s {
   std::vector<int64_t> up_ptr;  // host offsets into up_list per level
   // matrix data
   h2::DBuf Vf, Vb, F, ET, Smat, Nmat;
+  // H2_F32_SBF16: the coupling matrices also in FP32, for products with FP64
+  // accumulation (the outer residual of iterative refinement); BF16 S serves the rest
+  h2::DBuf Smat32;
   // E_c = E_x (x) E_y (x) E_z: per cluster the three m x m one-dimensional factors,
   // E1[c][d][i][j] = l_j(xi_i) along axis d (i child point, j parent polynomial)
   h2::DBuf E1;
@@ -94,6 +97,12 @@ struct h2_handle_s {
   // tile choices (0: the built-in rule), set by h2_tune or h2_set_tuning
   int tune_pass = 0;  // right-hand sides per many-RHS pass: 32 or 64
   int tune_slot = 0;  // lanes per block-row slot of the small-k coupling: 16 or 32
+  bool overwrite = false;  // the current product assigns y <- alpha G~ x (H2_OVERWRITE)
+  // h2_solve: the Krylov solver's workspace and its pinned status (kept between
+  // calls, grown when a call needs more)
+  h2::DBuf kws;
+  double* kstat = nullptr;
+  int kstat_n = 0;
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> events;     // pool
@@ -110,8 +119,8 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
 bool matvec_multi_supported(const h2_handle_s& H);
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
                   double alpha, hipStream_t s);
-int solve(h2_handle_s& H, const void* b, void* z, const h2_solve_params& p, h2_solve_info& info,
-          hipStream_t s);
+int solve_multi(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+                const h2_solve_params& p, h2_solve_info& info, hipStream_t st);
 void krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* W,
                  int64_t wr, void* h, hipStream_t st);
 void krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* h,

@@ -94,11 +94,12 @@ __global__ void permute_in(int64_t n, const int32_t* __restrict__ perm, const XT
 
 template <typename XT, typename AT>
 __global__ void permute_out(int64_t n, const int32_t* __restrict__ perm, const AT* __restrict__ yc, XT* __restrict__ y,
-                            double alpha) {
+                            double alpha, bool ow) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p < n) {
     const int32_t t = perm[p];
-    y[t] = static_cast<XT>(static_cast<double>(y[t]) + alpha * static_cast<double>(yc[p]));
+    const double y0 = ow ? 0.0 : static_cast<double>(y[t]);
+    y[t] = static_cast<XT>(y0 + alpha * static_cast<double>(yc[p]));
   }
 }
 
@@ -936,7 +937,7 @@ __global__ void permute_out_sym(int64_t n, const int32_t* __restrict__ perm, con
                                 const int32_t* __restrict__ leaves, const int32_t* __restrict__ cbegin,
                                 const int64_t* __restrict__ in_ptr, const int64_t* __restrict__ in_slot,
                                 const AT* __restrict__ scratch, const AT* __restrict__ yc, XT* __restrict__ y,
-                                double alpha) {
+                                double alpha, bool ow) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int32_t l = leaf_of_pos[p];
@@ -944,7 +945,8 @@ __global__ void permute_out_sym(int64_t n, const int32_t* __restrict__ perm, con
   AT v = yc[p];
   for (int64_t i = in_ptr[l]; i < in_ptr[l + 1]; ++i) v += scratch[in_slot[i] + off];
   const int64_t t = perm[p];
-  y[t] = static_cast<XT>(static_cast<double>(y[t]) + alpha * static_cast<double>(v));
+  const double y0 = ow ? 0.0 : static_cast<double>(y[t]);
+  y[t] = static_cast<XT>(y0 + alpha * static_cast<double>(v));
 }
 
 // ---------------------------------------------------------------- complex kernels (Helmholtz)
@@ -964,12 +966,14 @@ __global__ void permute_in_c(int64_t n, const int32_t* __restrict__ perm, const 
 
 template <typename XT, typename AT>
 __global__ void permute_out_c(int64_t n, const int32_t* __restrict__ perm, const AT* __restrict__ yr,
-                              const AT* __restrict__ yi, XT* __restrict__ y, double alpha) {
+                              const AT* __restrict__ yi, XT* __restrict__ y, double alpha, bool ow) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p < n) {
     const int64_t t = perm[p];
-    y[2 * t] = static_cast<XT>(static_cast<double>(y[2 * t]) + alpha * static_cast<double>(yr[p]));
-    y[2 * t + 1] = static_cast<XT>(static_cast<double>(y[2 * t + 1]) + alpha * static_cast<double>(yi[p]));
+    const double y0r = ow ? 0.0 : static_cast<double>(y[2 * t]);
+    const double y0i = ow ? 0.0 : static_cast<double>(y[2 * t + 1]);
+    y[2 * t] = static_cast<XT>(y0r + alpha * static_cast<double>(yr[p]));
+    y[2 * t + 1] = static_cast<XT>(y0i + alpha * static_cast<double>(yi[p]));
   }
 }
 
@@ -1181,6 +1185,9 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
   AT* yc = H.yc.as<AT>();
   AT* xh = H.xhat.as<AT>();
   AT* yh = H.yhat.as<AT>();
+  // BF16 storage keeps an FP32 copy of S: FP32 coupling data there is that copy
+  const SST* Sm = (std::is_same<SST, float>::value && H.P.storage == H2_F32_SBF16) ? H.Smat32.as<SST>()
+                                                                                    : H.Smat.as<SST>();
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
   if (H.prof) {
     e0 = prof_event(H);
@@ -1199,16 +1206,15 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
     else launch_otf<float, AT>(H, xh, yh, st);
   } else if (S.sym_s) {
     coupling64_sym<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
-                                               H.Smat.as<SST>(), xh, yh, H.scr_s.as<AT>());
+                                               Sm, xh, yh, H.scr_s.as<AT>());
     adm_gather<AT><<<blocks_for(nc, 4), 256, 0, st>>>(nc, H.adm_in_ptr.as<int64_t>(), H.adm_in_blk.as<int64_t>(),
                                                       H.scr_s.as<AT>(), yh);
   } else if (k == 64) {
-    coupling64<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), H.Smat.as<SST>(),
+    coupling64<SST, AT><<<nc, 256, 0, st>>>(nc, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(), Sm,
                                            xh, yh);
   } else if (k <= 32) {
     const int64_t* ap = H.adm_ptr.as<int64_t>();
     const int32_t* ac = H.adm_col.as<int32_t>();
-    const SST* Sm = H.Smat.as<SST>();
     const unsigned g = blocks_for(nc, 4);
     // slots of 16 lanes cover k <= 16; 32 lanes cover every k here (tuned choice)
     const bool rb16 = k <= 16 && H.tune_slot != 32;
@@ -1229,7 +1235,7 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
     }
   } else {
     coupling_any<SST, AT><<<nc, 256, 0, st>>>(nc, k, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
-                                             H.Smat.as<SST>(), xh, yh);
+                                             Sm, xh, yh);
   }
   if (H.prof) {
     e2 = prof_event(H);
@@ -1248,13 +1254,13 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
                                                   yc, H.scr_n.as<AT>());
     permute_out_sym<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(
         n, H.perm.as<int32_t>(), H.leaf_of_pos.as<int32_t>(), H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
-        H.near_in_ptr.as<int64_t>(), H.near_in_slot.as<int64_t>(), H.scr_n.as<AT>(), yc, y, alpha);
+        H.near_in_ptr.as<int64_t>(), H.near_in_slot.as<int64_t>(), H.scr_n.as<AT>(), yc, y, alpha, H.overwrite);
   } else {
     near_backward<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                               H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
                                               H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
                                               H.Vb.as<ST>(), xc, yh, yc);
-    permute_out<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), yc, y, alpha);
+    permute_out<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), yc, y, alpha, H.overwrite);
   }
   H2_HIP(hipGetLastError());
   if (H.prof) {
@@ -1334,7 +1340,8 @@ void matvec_complex(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_
                                               H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
                                               H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
                                               H.Vb.as<ST>(), xr, xi, yhr, yhi, ycr, yci);
-  permute_out_c<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), ycr, yci, y, alpha);
+  permute_out_c<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), ycr, yci, y, alpha,
+                                                            H.overwrite);
   H2_HIP(hipGetLastError());
   if (H.prof) {
     e4 = prof_event(H);
@@ -1369,6 +1376,7 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
   if (nrhs > 0 && (x == nullptr || y == nullptr)) throw Error(H2_EINVAL, "x and y must not be NULL");
   if (ldx < H.S.n || ldy < H.S.n) throw Error(H2_EINVAL, "leading dimension smaller than n");
   const bool acc64 = (flags & H2_ACC_F64) != 0;
+  H.overwrite = (flags & H2_OVERWRITE) != 0;
   if (cx) {
     if (nrhs >= 2 && !acc64 && matvec_multi_supported(H)) {
       matvec_multi(H, nrhs, dtype, x, ldx, y, ldy, alpha, st);
@@ -1398,8 +1406,8 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
         if (acc64) matvec_x<float, float, double>(H, dtype, xj, yj, alpha, st);
         else matvec_x<float, float, float>(H, dtype, xj, yj, alpha, st);
         break;
-      default:
-        if (acc64) matvec_x<bf16, float, double>(H, dtype, xj, yj, alpha, st);
+      default:  // BF16 S; FP64 accumulation applies the FP32 copy of S
+        if (acc64) matvec_x<float, float, double>(H, dtype, xj, yj, alpha, st);
         else matvec_x<bf16, float, float>(H, dtype, xj, yj, alpha, st);
     }
   }

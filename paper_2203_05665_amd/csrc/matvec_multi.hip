@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void mpermute_in(int64_t n, int rcur, const in
 template <typename XT, int RP>
 __global__ __launch_bounds__(256) void mpermute_out(int64_t n, int rcur, const int32_t* __restrict__ perm,
                                                     const float* __restrict__ yc, XT* __restrict__ y, int64_t ldy,
-                                                    double alpha) {
+                                                    double alpha, bool ow) {
   __shared__ float tile[64][RP + 1];
   const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
   for (int idx = threadIdx.x; idx < 64 * RP; idx += 256) {
@@ -196,7 +196,8 @@ __global__ __launch_bounds__(256) void mpermute_out(int64_t n, int rcur, const i
     const int64_t p = p0 + pl;
     if (j < rcur && p < n) {
       XT* dst = y + static_cast<int64_t>(j) * ldy + perm[p];
-      *dst = static_cast<XT>(static_cast<double>(*dst) + alpha * static_cast<double>(tile[pl][j]));
+      const double y0 = ow ? 0.0 : static_cast<double>(*dst);
+      *dst = static_cast<XT>(y0 + alpha * static_cast<double>(tile[pl][j]));
     }
   }
 }
@@ -640,7 +641,7 @@ __global__ __launch_bounds__(256) void mpermute_in_c(int64_t n, int rcur, const 
 template <typename XT>
 __global__ __launch_bounds__(256) void mpermute_out_c(int64_t n, int rcur, const int32_t* __restrict__ perm,
                                                       const float* __restrict__ yc, XT* __restrict__ y, int64_t ldy,
-                                                      double alpha) {
+                                                      double alpha, bool ow) {
   __shared__ float tile[64][33];
   const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
   for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
@@ -654,7 +655,8 @@ __global__ __launch_bounds__(256) void mpermute_out_c(int64_t n, int rcur, const
     const int64_t p = p0 + pl;
     if (jc < rcur && p < n) {
       XT* dst = y + 2 * (static_cast<int64_t>(jc) * ldy + perm[p]) + part;
-      *dst = static_cast<XT>(static_cast<double>(*dst) + alpha * static_cast<double>(tile[pl][16 * part + jc]));
+      const double y0 = ow ? 0.0 : static_cast<double>(*dst);
+      *dst = static_cast<XT>(y0 + alpha * static_cast<double>(tile[pl][16 * part + jc]));
     }
   }
 }
@@ -1070,7 +1072,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
                                                 H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
                                                 H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
                                                 H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
-  mpermute_out<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha);
+  mpermute_out<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
   H2_HIP(hipGetLastError());
   if (H.prof) {
     e4 = prof_event(H);
@@ -1151,7 +1153,7 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
                                                 H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
                                                 H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
                                                 H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
-  mpermute_out_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha);
+  mpermute_out_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
   H2_HIP(hipGetLastError());
   if (H.prof) {
     e4 = prof_event(H);

@@ -21,7 +21,9 @@ H2_OK, H2_EINVAL, H2_ENOMEM, H2_EHIP, H2_ENOTCONV, H2_EINTERNAL = 0, -1, -2, -3,
 H2_LAPLACE, H2_HELMHOLTZ, H2_TEST_ONE, H2_TEST_BILINEAR, H2_TEST_QUADRATIC = 0, 1, 2, 3, 4
 H2_F64, H2_F32, H2_F32_SBF16 = 0, 1, 2
 H2_R64, H2_R32, H2_C128, H2_C64 = 0, 1, 2, 3
-H2_ACC_F64 = 1
+H2_ACC_F64, H2_OVERWRITE = 1, 2
+H2_KS_PRODUCT, H2_KS_DONE, H2_KS_NOTCONV, H2_KS_FAILED = 1, 2, 3, 4
+KS_STATES = {H2_KS_PRODUCT: "product", H2_KS_DONE: "done", H2_KS_NOTCONV: "not_converged", H2_KS_FAILED: "failed"}
 H2_HOST_ONLY, H2_COUPLING_OTF, H2_SYMMETRIC, H2_SYMMETRIC_NEAR = 1, 2, 4, 8
 H2_CG, H2_GMRES = 0, 1
 (H2_X_PERM, H2_X_CLUSTERS, H2_X_BOXES, H2_X_ADM, H2_X_NEAR, H2_X_DFS, H2_X_V, H2_X_E, H2_X_S,
@@ -63,6 +65,11 @@ class h2_solve_info(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class h2_krylov_status(C.Structure):
+    _fields_ = [("state", C.c_int), ("iterations", C.c_int), ("outer", C.c_int), ("products", C.c_int),
+                ("rel_residual", C.c_double), ("message", C.c_char * 128)]
+
+
 class h2_recompress_info(C.Structure):
     _fields_ = [("rank", C.c_int64), ("rank_before", C.c_int64), ("discarded", C.c_double),
                 ("seconds", C.c_double), ("bytes_before", C.c_int64), ("bytes_after", C.c_int64)]
@@ -87,8 +94,20 @@ def lib():
         L.build_h2.argtypes = [C.POINTER(h2_mesh), C.POINTER(h2_params), C.POINTER(C.c_void_p)]
         L.h2_matvec.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                 C.c_double, C.c_int, C.c_void_p]
-        L.h2_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(h2_solve_params),
-                               C.POINTER(h2_solve_info), C.c_void_p]
+        L.h2_solve.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                               C.POINTER(h2_solve_params), C.POINTER(h2_solve_info), C.c_void_p]
+        L.h2_krylov_workspace.argtypes = [C.c_int, C.c_int64, C.c_int, C.POINTER(h2_solve_params)]
+        L.h2_krylov_workspace.restype = C.c_int64
+        L.h2_krylov_create.argtypes = [C.c_int, C.c_int64, C.c_int, C.POINTER(h2_solve_params), C.c_void_p,
+                                       C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.h2_krylov_begin.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        L.h2_krylov_next.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int), C.c_void_p]
+        L.h2_krylov_advance.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.h2_krylov_poll.argtypes = [C.c_void_p, C.POINTER(h2_krylov_status)]
+        L.h2_krylov_residuals.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.h2_krylov_solution.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.h2_krylov_destroy.argtypes = [C.c_void_p]
+        L.h2_krylov_destroy.restype = None
         L.h2_info.argtypes = [C.c_void_p, C.POINTER(h2_stats)]
         L.h2_free.argtypes = [C.c_void_p]
         L.h2_free.restype = None
@@ -104,7 +123,9 @@ def lib():
         L.h2_tune.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(h2_tune_info), C.c_void_p]
         L.h2_set_tuning.argtypes = [C.c_void_p, C.c_int, C.c_int]
         for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
-                  "h2_krylov_dots", "h2_krylov_update", "h2_recompress", "h2_tune", "h2_set_tuning"):
+                  "h2_krylov_dots", "h2_krylov_update", "h2_recompress", "h2_tune", "h2_set_tuning",
+                  "h2_krylov_create", "h2_krylov_begin", "h2_krylov_next", "h2_krylov_advance", "h2_krylov_poll",
+                  "h2_krylov_residuals", "h2_krylov_solution"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -150,8 +171,9 @@ def _stream(stream):
     return torch.cuda.current_stream().cuda_stream
 
 
-def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
-    """y <- y + alpha G~ x for torch CUDA tensors x, y (n or n x nrhs, Fortran order)."""
+def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None, overwrite=False):
+    """y <- y + alpha G~ x (or y <- alpha G~ x with overwrite) for torch CUDA tensors
+    x, y (n or n x nrhs, Fortran order)."""
     import torch
     dtypes = {torch.float64: H2_R64, torch.float32: H2_R32, torch.complex128: H2_C128, torch.complex64: H2_C64}
     if x.dtype != y.dtype or x.dtype not in dtypes:
@@ -171,34 +193,129 @@ def h2_matvec(h, x, y, alpha=1.0, acc64=False, stream=None):
         raise ValueError("columns must be contiguous")
     dt = dtypes[x.dtype]
     _check(lib().h2_matvec(h, nrhs, dt, x.data_ptr(), ldx, y.data_ptr(), ldy, float(alpha),
-                           H2_ACC_F64 if acc64 else 0, _stream(stream)))
+                           (H2_ACC_F64 if acc64 else 0) | (H2_OVERWRITE if overwrite else 0), _stream(stream)))
     return y
+
+
+def _block(v, n, name):
+    """(pointer, nrhs, ld) of a device vector or Fortran-ordered n x nrhs block."""
+    if v.dim() == 1:
+        v2 = v[:, None]
+    elif v.dim() == 2:
+        v2 = v
+    else:
+        raise ValueError("%s must have shape (n,) or (n, nrhs)" % name)
+    if v2.shape[0] != n:
+        raise ValueError("%s has %d rows, the matrix has %d" % (name, v2.shape[0], n))
+    r = v2.shape[1]
+    if r > 0 and n > 1 and v2.stride(0) != 1:
+        raise ValueError("%s: columns must be contiguous" % name)
+    ld = v2.stride(1) if r > 1 else n
+    if r > 1 and ld < n:
+        raise ValueError("%s: columns overlap" % name)
+    return v2.data_ptr(), r, ld
+
+
+def solve_params(method="cg", rtol=1e-8, maxit=1000, restart=50, refine=False, inner_rtol=1e-4):
+    return h2_solve_params(H2_CG if method == "cg" else H2_GMRES, int(restart), int(maxit), float(rtol),
+                           1 if refine else 0, float(inner_rtol))
 
 
 def h2_solve(h, b, z, method="cg", rtol=1e-8, maxit=1000, restart=50, refine=False, inner_rtol=1e-4,
              stream=None, check=True):
-    """Solves G~ z = b (float64, or complex128 for Helmholtz, device tensors); z holds
-    the initial guess and the result."""
+    """Solves G~ Z = B for float64 (complex128 for Helmholtz) device blocks b, z of
+    shape (n,) or (n, nrhs) with contiguous columns; z holds the initial guess
+    and the result."""
     import torch
     want = torch.complex128 if b.is_complex() else torch.float64
     if b.dtype != want or z.dtype != want:
         raise TypeError("b and z must be float64 (complex128 for Helmholtz) tensors")
     n = h2_info(h)["n"]
-    for nm, v in (("b", b), ("z", z)):
-        if not (v.dim() == 1 or (v.dim() == 2 and v.shape[1] == 1)) or v.shape[0] != n:
-            raise ValueError("%s must have shape (n,) or (n, 1) with n = %d, got %s" % (nm, n, tuple(v.shape)))
-        if not v.is_contiguous():
-            raise ValueError("%s must be contiguous" % nm)
+    pb, rb, ldb = _block(b, n, "b")
+    pz, rz, ldz = _block(z, n, "z")
+    if rb != rz:
+        raise ValueError("b and z must have the same number of columns")
     if not (b.is_cuda and z.is_cuda):
         raise TypeError("b and z must be device tensors")
-    p = h2_solve_params(H2_CG if method == "cg" else H2_GMRES, int(restart), int(maxit), float(rtol),
-                        1 if refine else 0, float(inner_rtol))
+    p = solve_params(method, rtol, maxit, restart, refine, inner_rtol)
     info = h2_solve_info()
-    rc = lib().h2_solve(h, b.data_ptr(), z.data_ptr(), C.byref(p), C.byref(info), _stream(stream))
+    dt = H2_C128 if b.is_complex() else H2_R64
+    rc = lib().h2_solve(h, rb, dt, pb, ldb, pz, ldz, C.byref(p), C.byref(info), _stream(stream))
     if rc != H2_ENOTCONV or check:
         _check(rc)
     return dict(iterations=info.iterations, outer=info.outer, rel_residual=info.rel_residual,
                 seconds=info.seconds, converged=rc == H2_OK)
+
+
+class KrylovSolve:
+    """The step-wise solver of include/h2.h (h2_krylov_*) on caller-owned device
+    workspace: `next` writes the block whose product the solve needs, `advance`
+    takes the product, `poll` (after the stream completed) decides."""
+
+    def __init__(self, n, nrhs, complex_, params, workspace_ptr, workspace_bytes, status_ptr=None):
+        self.n, self.nrhs = int(n), int(nrhs)
+        self.dtype = H2_C128 if complex_ else H2_R64
+        self.params = params
+        k = C.c_void_p()
+        _check(lib().h2_krylov_create(self.dtype, self.n, self.nrhs, C.byref(params), workspace_ptr,
+                                      int(workspace_bytes), status_ptr, C.byref(k)))
+        self.k = k.value
+        self._res = (C.c_double * self.nrhs)()
+
+    @staticmethod
+    def workspace_bytes(n, nrhs, complex_, params):
+        b = lib().h2_krylov_workspace(H2_C128 if complex_ else H2_R64, int(n), int(nrhs), C.byref(params))
+        if b < 0:
+            raise ValueError("invalid solver parameters")
+        return int(b)
+
+    def begin(self, b, z0=None, stream=None):
+        pb, _, ldb = _block(b, self.n, "b")
+        pz, ldz = (None, self.n) if z0 is None else _block(z0, self.n, "z0")[::2]
+        _check(lib().h2_krylov_begin(self.k, pb, ldb, pz, ldz, _stream(stream)))
+
+    def next(self, x=None, stream=None):
+        """(state, flags); with x = None only reports what the next product needs."""
+        fl = C.c_int(0)
+        if x is None:
+            rc = lib().h2_krylov_next(self.k, None, 0, C.byref(fl), _stream(stream))
+        else:
+            px, _, ldx = _block(x, self.n, "x")
+            rc = lib().h2_krylov_next(self.k, px, ldx, C.byref(fl), _stream(stream))
+        if rc < 0:
+            _check(rc)
+        return rc, fl.value
+
+    def advance(self, y, stream=None):
+        py, _, ldy = _block(y, self.n, "y")
+        _check(lib().h2_krylov_advance(self.k, py, ldy, _stream(stream)))
+
+    def poll(self):
+        st = h2_krylov_status()
+        rc = lib().h2_krylov_poll(self.k, C.byref(st))
+        if rc < 0:
+            _check(rc)
+        return dict(state=KS_STATES[st.state], iterations=st.iterations, outer=st.outer, products=st.products,
+                    rel_residual=st.rel_residual, message=st.message.decode())
+
+    def residuals(self):
+        _check(lib().h2_krylov_residuals(self.k, self._res))
+        return np.array(self._res[:], dtype=np.float64)
+
+    def solution(self, z, stream=None):
+        pz, _, ldz = _block(z, self.n, "z")
+        _check(lib().h2_krylov_solution(self.k, pz, ldz, _stream(stream)))
+
+    def close(self):
+        if self.k:
+            lib().h2_krylov_destroy(self.k)
+            self.k = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _kdtype(t):
@@ -309,11 +426,11 @@ class H2Matrix:
         self.info = h2_info(self.h)
         self.n = self.info["n"]
 
-    def matvec(self, x, y=None, alpha=1.0, acc64=False, stream=None):
+    def matvec(self, x, y=None, alpha=1.0, acc64=False, stream=None, overwrite=False):
         import torch
         if y is None:
             y = torch.zeros_like(x)
-        return h2_matvec(self.h, x, y, alpha, acc64, stream)
+        return h2_matvec(self.h, x, y, alpha, acc64, stream, overwrite)
 
     def recompress(self, eps, max_rank=0, stream=None):
         """Replace V, E and S by a recompressed representation of rank k' (see h2_recompress)."""

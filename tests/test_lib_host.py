@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "h2.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -217,12 +217,14 @@ def test_wrapper_rejects_bad_vector_shapes():
         with pytest.raises(TypeError):                         # right shape, but host memory
             h2.h2_matvec(h, ok, ok.clone())
         for b in (torch.zeros(n - 1, dtype=torch.float64), torch.zeros(n, 2, dtype=torch.float64),
-                  torch.zeros(2 * n, dtype=torch.float64)[::2]):
+                  torch.zeros(2 * n, dtype=torch.float64)[::2], torch.zeros(2, n, 1, dtype=torch.float64)):
             with pytest.raises(ValueError):
                 h2.h2_solve(h, b, torch.zeros(n, dtype=torch.float64))
             with pytest.raises(ValueError):
-                h2.h2_solve(h, torch.zeros(n, dtype=torch.float64), b.clone() if b.is_contiguous() else b)
+                h2.h2_solve(h, torch.zeros(n, dtype=torch.float64), b)
         with pytest.raises(TypeError):
             h2.h2_solve(h, ok, ok.clone())
+        with pytest.raises(TypeError):                           # n x 2 Fortran blocks are accepted, on a device
+            h2.h2_solve(h, torch.zeros(2, n, dtype=torch.float64).t(), torch.zeros(2, n, dtype=torch.float64).t())
     finally:
         h2.h2_free(h)

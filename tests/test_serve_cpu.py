@@ -11,29 +11,41 @@ import torch
 
 import h2_inputs as I
 from paper_2203_05665_amd.serve import H2Server
+from tests import cpu_krylov
 
 torch.set_default_dtype(torch.float64)
 
 
+class _Dense:
+    def __init__(self, A, width):
+        n = A.shape[0]
+        self.A = A
+        self.X = torch.zeros((width, n), dtype=A.dtype).t()
+        self.Y = torch.zeros((width, n), dtype=A.dtype).t()
+
+
 class DenseBackend:
     """Products with a dense matrix on the CPU; optional FP32 rounding of the
-    operator to exercise the refinement path (acc64 uses the same rounded
-    entries with FP64 accumulation)."""
+    operator to exercise the refinement path (FP64 accumulation uses the same
+    rounded entries with FP64 accumulation); Krylov steps by the CPU model of the
+    library's step-wise solver."""
 
     device = torch.device("cpu")
+    torch = torch
 
-    def __init__(self, refine=False, poison=False, nbytes_per_entry=8):
+    def __init__(self, refine=False, poison=False, nbytes_per_entry=8, product_width=64):
         self._refine = refine
         self.poison = poison
         self.built, self.freed, self.products = 0, 0, 0
         self.nb = nbytes_per_entry
+        self.product_width = product_width
+        self.widths = []
 
     def estimate(self, V, T, kernel, kappa):
         return int(T.shape[0] ** 2 * self.nb)
 
     def build(self, V, T, kernel, kappa):
         n = T.shape[0]
-        rng = np.random.default_rng(n + int(10 * kappa))
         P = V[T]
         c = P.mean(1)
         d = np.linalg.norm(c[:, None] - c[None], axis=-1)
@@ -44,20 +56,25 @@ class DenseBackend:
         if self._refine:
             A = A.astype(np.complex64 if kernel == "helmholtz" else np.float32).astype(A.dtype)
         self.built += 1
-        return torch.tensor(A), int(n * n * self.nb)
+        return _Dense(torch.tensor(A), self.product_width), int(n * n * self.nb)
 
-    def matvec(self, A, X, Y, acc64, stream):
+    def buffers(self, S):
+        return S.X, S.Y
+
+    def matvec(self, S, ncols, flags, stream):
         self.products += 1
+        self.widths.append(ncols)
+        X, Y, A = S.X[:, :ncols], S.Y[:, :ncols], S.A
         if self.poison:
-            Y += float("nan")
+            Y.fill_(float("nan"))
             return
-        if self._refine and not acc64:
+        if self._refine and not flags & cpu_krylov.ACC_F64:
             lo = torch.complex64 if A.is_complex() else torch.float32
-            Y += (A.to(lo) @ X.to(lo)).to(Y.dtype)
+            Y.copy_((A.to(lo) @ X.to(lo)).to(Y.dtype))
         else:
-            Y += A @ X
+            Y.copy_(A @ X)
 
-    def free(self, A):
+    def free(self, S):
         self.freed += 1
 
     def new_stream(self):
@@ -65,6 +82,33 @@ class DenseBackend:
 
     def refine(self):
         return self._refine
+
+    def request_arena(self, nbytes):
+        return None
+
+    def status_pool(self, slots, per_slot):
+        return None
+
+    def solver_params(self, method, rtol, maxit, restart, refine, inner_rtol):
+        return cpu_krylov.params(method, rtol, maxit, restart, refine, inner_rtol)
+
+    def workspace_bytes(self, n, r, cx, p):
+        return cpu_krylov.workspace_bytes(n, r, cx, p)
+
+    def new_solver(self, n, r, cx, p, ws_ptr, ws_bytes, status_ptr):
+        return cpu_krylov.CPUKrylov(n, r, cx, p)
+
+    def to_device(self, b, cx):
+        b = torch.as_tensor(np.asarray(b))
+        if b.dim() == 1:
+            b = b[:, None]
+        return b.to(torch.complex128 if cx else torch.float64).t().contiguous().t()
+
+    def empty_like(self, b):
+        return torch.zeros((b.shape[1], b.shape[0]), dtype=b.dtype).t()
+
+    def all_finite(self, b):
+        return bool(torch.isfinite(b).all())
 
 
 class Clock:
@@ -76,8 +120,8 @@ class Clock:
         return self.t
 
 
-def make_server(backend, budget=1e12, slots=8):
-    S = H2Server(backend, mem_budget=budget, max_active=slots, clock=Clock())
+def make_server(backend, budget=1e12, slots=8, vec_budget=None):
+    S = H2Server(backend, mem_budget=budget, max_active=slots, clock=Clock(), vec_budget=vec_budget)
     for r in (1, 2):
         S.register_mesh("sphere%d" % r, *I.icosphere(r))
     S.register_mesh("cube2", *I.cube_surface(2))
@@ -86,7 +130,7 @@ def make_server(backend, budget=1e12, slots=8):
 
 def dense(backend, S, mesh, kernel="laplace", kappa=0.0):
     A, _ = backend.build(*S.meshes[mesh], kernel, kappa)
-    return A.numpy()
+    return A.A.numpy()
 
 
 def test_cg_and_gmres_requests_solve():
@@ -119,7 +163,7 @@ def test_refinement_reaches_tolerance_of_rounded_operator():
     for req, A in ((q, dense(be, S, "sphere2")), (qc, dense(be, S, "sphere2", "helmholtz", 4.0))):
         assert req.status == "done"
         z = req.result.numpy()[:, 0]
-        rhs = req.b.numpy()[0]          # requests hold right-hand sides as rows
+        rhs = req.b.numpy()[:, 0]
         assert np.linalg.norm(A @ z - rhs) <= 1.01e-10 * np.linalg.norm(rhs)
 
 
@@ -171,14 +215,18 @@ def test_arrivals_and_slots():
     assert max(seen_active) == 2
 
 
+def _ws(n, r=1, method="cg"):
+    return cpu_krylov.workspace_bytes(n, r, False, cpu_krylov.params(method))
+
+
 def test_memory_budget_admission_and_eviction():
     be = DenseBackend()
     n1 = I.icosphere(1)[1].shape[0]
     n2 = I.icosphere(2)[1].shape[0]
-    # room for the larger structure plus one request's vectors (8 vectors of n2
-    # doubles), but not for both structures at once
-    budget = n2 * n2 * 8 + 8 * n2 * 8 + n1 * n1 * 8 // 2
-    S = make_server(be, budget=budget)
+    vec = 4 * _ws(n2)
+    # room for the request arena and the larger structure, not for both structures
+    budget = vec + n2 * n2 * 8 + n1 * n1 * 8 // 2
+    S = make_server(be, budget=budget, vec_budget=vec)
     rng = np.random.default_rng(5)
     a = S.submit("sphere2", rng.standard_normal(n2), rtol=1e-8, arrival=0.0)
     b = S.submit("sphere1", rng.standard_normal(n1), rtol=1e-8, arrival=0.0)
@@ -187,6 +235,32 @@ def test_memory_budget_admission_and_eviction():
     assert b.start >= a.finish            # waited until the first structure became idle
     assert be.freed >= 1                   # the idle structure was evicted
     assert S.used_bytes() <= budget
+
+
+def test_requests_wait_for_room_in_the_vector_arena():
+    """The request arena holds one request's vectors: a second request on the
+    same (resident) structure starts when the first one has released them."""
+    be = DenseBackend()
+    n2 = I.icosphere(2)[1].shape[0]
+    S = make_server(be, vec_budget=_ws(n2) + 255)
+    rng = np.random.default_rng(7)
+    a = S.submit("sphere2", rng.standard_normal(n2), rtol=1e-8, arrival=0.0)
+    c = S.submit("sphere2", rng.standard_normal(n2), rtol=1e-8, arrival=0.0)
+    S.run()
+    assert a.status == c.status == "done", S.stats()["errors"]
+    assert c.start >= a.finish and be.built == 1
+    assert S.arena.used() == 0 and sorted(S.free_slots) == list(range(S.max_active))
+
+
+def test_request_vectors_larger_than_the_arena_fail_cleanly():
+    be = DenseBackend()
+    n2 = I.icosphere(2)[1].shape[0]
+    S = make_server(be, vec_budget=_ws(n2) // 2)
+    q = S.submit("sphere2", np.ones(n2), rtol=1e-8)
+    S.run()
+    assert q.status == "failed" and "vectors do not fit" in q.error
+    w = S.submit("sphere2", np.ones((n2, 65)), rtol=1e-8)
+    assert w.status == "failed" and "right-hand sides" in w.error
 
 
 def test_structure_larger_than_budget_fails_cleanly():
@@ -226,25 +300,6 @@ def test_non_convergence_and_poisoned_products():
     assert "a product returned a non-finite entry" in p.error       # blamed on the product, not the solver
 
 
-def test_resident_structure_makes_room_for_request_vectors():
-    """A request whose structure is already resident evicts other idle
-    structures when its vectors would not fit beside them."""
-    be = DenseBackend()
-    n1 = I.icosphere(1)[1].shape[0]
-    n2 = I.icosphere(2)[1].shape[0]
-    v2 = 8 * n2 * 8                       # vectors of a one-column CG request on sphere2
-    budget = n2 * n2 * 8 + n1 * n1 * 8 + v2 // 2
-    S = make_server(be, budget=budget)
-    rng = np.random.default_rng(7)
-    a = S.submit("sphere2", rng.standard_normal(n2), rtol=1e-8, arrival=0.0)
-    b = S.submit("sphere1", rng.standard_normal(n1), rtol=1e-8, arrival=1.0)
-    c = S.submit("sphere2", rng.standard_normal(n2), rtol=1e-8, arrival=2.0)
-    S.run()
-    assert [q.status for q in (a, b, c)] == ["done"] * 3, S.stats()["errors"]
-    assert be.built == 2 and be.freed == 1          # sphere1 evicted, sphere2 kept
-    assert S.stats()["errors"] == {}
-
-
 def test_failures_are_reported():
     S = make_server(DenseBackend())
     S.submit("nope", np.ones(10))
@@ -282,5 +337,26 @@ def test_mixed_stream_of_wide_requests_has_no_failures():
     for q in reqs:
         A = dense(be, S, q.mesh, q.kernel, q.kappa)
         Z = q.result.numpy()
-        Bq = q.b.numpy().T
+        Bq = q.b.numpy()
         assert np.linalg.norm(A @ Z - Bq) <= 1.01e-8 * np.linalg.norm(Bq) * np.sqrt(Bq.shape[1])
+
+
+def test_products_are_chunked_to_the_buffer_width():
+    """With room for 4 columns per product, six requests of 1-3 columns are served
+    by several products per tick, none wider than 4 columns, and each result is
+    the same as with one wide product."""
+    rng = np.random.default_rng(9)
+    n = I.icosphere(2)[1].shape[0]
+    Bs = [rng.standard_normal((n, 1 + i % 3)) for i in range(6)]
+    out = {}
+    for width in (4, 64):
+        be = DenseBackend(product_width=width)
+        S = make_server(be)
+        reqs = [S.submit("sphere2", B, rtol=1e-10, arrival=0.0) for B in Bs]
+        S.run()
+        assert all(q.status == "done" for q in reqs)
+        assert max(be.widths) <= width
+        out[width] = [q.result.numpy() for q in reqs]
+    assert max(be.widths) > 4
+    for a, b in zip(out[4], out[64]):
+        assert np.array_equal(a, b)
