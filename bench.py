@@ -31,6 +31,7 @@ WORKLOADS = {
     "sphere1310k_m4_f64": ("sphere", 8, 4, 64, "f64", 3),
     "sphere327k_m4_f64": ("sphere", 7, 4, 64, "f64", 2),
     "cube786k_m4_f32": ("cube", 256, 4, 64, "f32", 4),
+    "sphere5120_m4_f64": ("sphere", 4, 4, 64, "f64", 2),
 }
 # the same products with the coupling matrices evaluated during the product
 OTF_WORKLOADS = {"sphere1310k_m4_f32_otf": "sphere1310k_m4_f32", "sphere1310k_m4_f64_otf": "sphere1310k_m4_f64"}
@@ -96,17 +97,11 @@ def graph_timing(A, x, y, torch, reps=20, warmup=5):
             "matvec_per_s_median": 1e3 / ms[len(ms) // 2]}
 
 
-def cpu_baseline_sample(kind, level, order, leaf, seed, budget_s=25.0):
-    """Oracle (FP64, Algorithms 1-3 as written) timed on samples of the same workload.
+_ORACLE = {}
 
-    Forward/backward transformation: Algorithm 1 and 2 on one subtree at depth 5
-    (about 1/32 of the clusters), scaled by the cluster count.  Interaction
-    phase: Algorithm 3 on the admissible and inadmissible leaves of the block
-    rows of a few random leaf clusters (matrices assembled first, then applied
-    and timed), scaled by |L+| and |L-|.
-    """
-    import numpy as np
 
+def _oracle_setup(kind, level, order, leaf, seed):
+    """The oracle's trees for the workload (built once, shared by forked workers)."""
     import h2_inputs as I
     from oracle.h2 import H2Oracle
     from oracle.kernels import Kernel
@@ -114,57 +109,131 @@ def cpu_baseline_sample(kind, level, order, leaf, seed, budget_s=25.0):
     V, T = I.mesh_for(kind, level)
     H = H2Oracle(V, T, Kernel(), m=order, leaf=leaf, eta=0.5, build_blocks=False)
     x = I.random_vector(H.mesh.n, seed, "normal")
-    ncl = len(H.tree.clusters)
-    sub = H.tree.root
-    while sub.level < 5 and sub.children:
-        sub = sub.children[0]
-    nsub = sum(1 for _ in _walk(sub))
-    xhat = [None] * ncl
-    t0 = time.perf_counter()
-    H.forward(sub, x, xhat)
-    t_fwd = time.perf_counter() - t0
-    yhat = [np.zeros(H.k) if v is None else v.copy() for v in xhat]
-    y = np.zeros(H.mesh.n)
-    t0 = time.perf_counter()
-    H.backward(sub, yhat, y)
-    t_bwd = time.perf_counter() - t0
-    # interaction sample
-    rng = np.random.default_rng(seed)
-    adm, near = [], []
-    t_start = time.perf_counter()
-    for lid in rng.permutation(len(H.tree.leaves)):
-        a, nn = H.row_blocks(H.tree.leaves[lid])
-        adm += a
-        near += nn
-        for t_, s_ in a:
-            H.S(t_, s_)
-            if xhat[s_.id] is None:
-                xhat[s_.id] = np.zeros(H.k)
-        for t_, s_ in nn:
-            H.N(t_, s_)
-        if time.perf_counter() - t_start > 0.6 * budget_s:
-            break
-    yh = np.zeros(H.k)
-    t0 = time.perf_counter()
-    for t_, s_ in adm:
-        yh = yh + H.S(t_, s_) @ xhat[s_.id]
-    t_adm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for t_, s_ in near:
-        y[t_.idx] += H.N(t_, s_) @ x[s_.idx]
-    t_near = time.perf_counter() - t0
-    from paper_2203_05665_amd import h2 as _h2  # structure counts only (host-only build)
-    hh = _h2.build_h2(V, T, order=order, leaf=leaf, eta=0.5, host_only=True)
-    info = _h2.h2_info(hh)
-    _h2.h2_free(hh)
-    est = (t_fwd + t_bwd) * ncl / nsub + t_adm * info["n_adm"] / max(1, len(adm)) + \
-        t_near * info["n_near"] / max(1, len(near))
-    cores = 1  # the oracle is sequential Python/NumPy; BLAS is pinned to one thread below
-    sample = ("oracle Algorithms 1-2 on a depth-5 subtree (%d of %d clusters) and Algorithm 3 on %d "
-              "admissible + %d inadmissible blocks (block rows of random leaves), FP64, matrices pre-assembled; "
-              "scaled to the whole product" % (nsub, ncl, len(adm), len(near)))
-    return {"value": 1.0 / est, "unit": "H2 matvecs/s", "cores": cores, "kind": "oracle",
-            "sample": sample, "est_seconds_per_matvec": est}
+    subs = [H.tree.root]
+    while subs[0].level < 5 and all(c.children for c in subs):
+        subs = [ch for c in subs for ch in c.children]
+    _ORACLE.update(H=H, x=x, subs=subs, seed=seed)
+
+
+def _oracle_sample(worker, budget_s):
+    """Oracle (FP64, Algorithms 1-3 as written) timed on a sample of the product.
+
+    Forward/backward transformation: Algorithms 1 and 2 on one subtree at depth
+    5 (about 1/32 of the clusters; worker w takes subtree w).  Interaction phase:
+    Algorithm 3 on the admissible and inadmissible leaves of the block rows of
+    random leaf clusters (matrices assembled first, then applied and timed)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    H, x, subs = _ORACLE["H"], _ORACLE["x"], _ORACLE["subs"]
+    with threadpool_limits(limits=1):
+        ncl = len(H.tree.clusters)
+        sub = subs[worker % len(subs)]
+        nsub = sum(1 for _ in _walk(sub))
+        xhat = [None] * ncl
+        t0 = time.perf_counter()
+        H.forward(sub, x, xhat)
+        t_fwd = time.perf_counter() - t0
+        yhat = [np.zeros(H.k) if v is None else v.copy() for v in xhat]
+        y = np.zeros(H.mesh.n)
+        t0 = time.perf_counter()
+        H.backward(sub, yhat, y)
+        t_bwd = time.perf_counter() - t0
+        rng = np.random.default_rng(_ORACLE["seed"] + 1000 * worker)
+        adm, near = [], []
+        t_start = time.perf_counter()
+        for lid in rng.permutation(len(H.tree.leaves)):
+            a, nn = H.row_blocks(H.tree.leaves[lid])
+            adm += a
+            near += nn
+            for t_, s_ in a:
+                H.S(t_, s_)
+                if xhat[s_.id] is None:
+                    xhat[s_.id] = np.zeros(H.k)
+            for t_, s_ in nn:
+                H.N(t_, s_)
+            if time.perf_counter() - t_start > 0.6 * budget_s:
+                break
+        yh = np.zeros(H.k)
+        t0 = time.perf_counter()
+        for t_, s_ in adm:
+            yh = yh + H.S(t_, s_) @ xhat[s_.id]
+        t_adm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for t_, s_ in near:
+            y[t_.idx] += H.N(t_, s_) @ x[s_.idx]
+        t_near = time.perf_counter() - t0
+    return dict(t_fwd=t_fwd, t_bwd=t_bwd, nsub=nsub, ncl=ncl, t_adm=t_adm, nadm=len(adm), t_near=t_near,
+                nnear=len(near))
+
+
+def cpu_baseline_child(args):
+    """Child process of the CPU baseline: the oracle on `workers` host cores, each
+    core timing its own sample (its own subtree and block rows); no GPU use."""
+    import multiprocessing as mp
+
+    kind, level, order, leaf, storage, seed = WORKLOADS[args.workload]
+    W = args.cpu_baseline_child
+    _oracle_setup(kind, level, order, leaf, seed)
+    budget = args.cpu_budget_s
+    if W == 1:
+        parts = [_oracle_sample(0, budget)]
+    else:
+        with mp.get_context("fork").Pool(W) as pool:
+            parts = pool.starmap(_oracle_sample, [(w, budget) for w in range(W)])
+    est = []
+    for p in parts:
+        est.append((p["t_fwd"] + p["t_bwd"]) * p["ncl"] / p["nsub"] + p["t_adm"] * args.n_adm / max(1, p["nadm"])
+                   + p["t_near"] * args.n_near / max(1, p["nnear"]))
+    # each core computes its share of the product at its own measured rate
+    rate = sum(1.0 / e for e in est)
+    sample = ("oracle Algorithms 1-2 on a depth-5 subtree (about 1/%d of the clusters) and Algorithm 3 on "
+              "%d admissible + %d inadmissible blocks (block rows of random leaves) per core, FP64, matrices "
+              "pre-assembled, one BLAS thread per process; scaled to the whole product, the cores' rates added"
+              % (len(_ORACLE["subs"]), sum(p["nadm"] for p in parts) // W, sum(p["nnear"] for p in parts) // W))
+    print(json.dumps({"value": rate, "unit": "H2 matvecs/s", "cores": W, "kind": "oracle", "sample": sample,
+                      "est_seconds_per_matvec_per_core": est}), flush=True)
+
+
+def cpu_baseline(args, kind_workload, n_adm, n_near, workers, budget_s):
+    """Runs the oracle baseline in a child process (fresh interpreter, no GPU)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", str(workers), "--workload",
+           kind_workload, "--n-adm", str(n_adm), "--n-near", str(n_near), "--cpu-budget-s", str(budget_s)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"value": None, "error": r.stderr[-2000:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def read_ceiling(torch, h2, gib=4.0, reps=10):
+    """HBM read rate of the library's read-only streaming kernel (16-byte
+    non-temporal loads, as the product kernels issue them) over `gib` GiB, far
+    beyond the caches; HIP events on the launch stream, mean over `reps`."""
+    nbytes = int(gib * (1 << 30))
+    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(8192, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        h2.h2_stream_read(buf, sink, stream=s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        h2.h2_stream_read(buf, sink, stream=s.cuda_stream)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del buf, sink
+    torch.cuda.empty_cache()
+    return {"kernel": "stream_read", "bytes_per_launch": nbytes, "avg_launch_ms": ms,
+            "GBs": nbytes / (ms * 1e-3) / 1e9}
 
 
 def copy_probe(torch, gib=2.0, reps=5):
@@ -290,16 +359,23 @@ def bench_helmholtz(args):
 
 
 def bench_multi(args):
-    """Many right-hand sides in one call (matrix-core path)."""
+    """Many right-hand sides in one call (matrix-core path): one JSON line."""
+    print(json.dumps(run_multi(args, args.workload, full=True)), flush=True)
+
+
+def run_multi(args, workload, full=True):
+    """The many-right-hand-side product on its workload; with full, also the
+    variant with the coupling evaluated during the product and the columns one
+    at a time."""
     import torch
 
     import h2_inputs as I
     from paper_2203_05665_amd import h2
 
-    kind, level, order, leaf, storage, seed, R = MULTI[args.workload]
+    kind, level, order, leaf, storage, seed, R = MULTI[workload]
     V, T = I.mesh_for(kind, level)
     n = T.shape[0]
-    log("bench: %s n=%d m=%d leaf=%d storage=%s nrhs=%d" % (args.workload, n, order, leaf, storage, R))
+    log("bench: %s n=%d m=%d leaf=%d storage=%s nrhs=%d" % (workload, n, order, leaf, storage, R))
     t0 = time.perf_counter()
     A = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage)
     torch.cuda.synchronize()
@@ -328,7 +404,7 @@ def bench_multi(args):
         "metric": "RHS x H2 matvecs/s", "value": R * args.steps / el, "unit": "rhs-matvec/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "mesh": "%s level %d" % (kind, level), "triangles": n,
+        "config": {"workload": workload, "mesh": "%s level %d" % (kind, level), "triangles": n,
                    "order_m": order, "k": k, "leaf": leaf, "eta": 0.5, "storage": storage, "rhs": R},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_F32_PEAK_TFS, "unit": "TFLOP/s",
                      "frac": achieved / MFMA_F32_PEAK_TFS, "traffic": None, "kernel": "mcoupling",
@@ -339,6 +415,10 @@ def bench_multi(args):
         "tuning": tuning, "graph_replay": graph,
     }
     A.close()
+    del A
+    torch.cuda.empty_cache()
+    if not full:
+        return out
     if not args.no_otf:
         log("bench: many right-hand sides with the coupling evaluated during the product")
         C = h2.H2Matrix(V, T, kernel="laplace", order=order, leaf=leaf, eta=0.5, storage=storage, coupling_otf=True)
@@ -363,11 +443,26 @@ def bench_multi(args):
     out["single_rhs_compare"] = {"value": max(3, args.steps) / el1, "unit": "matvec/s",
                                  "speedup_per_rhs": (R * args.steps / el) / (max(3, args.steps) / el1)}
     B.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_serve(args):
-    """Poisson stream of solve requests served with continuous batching."""
+    """Poisson stream of solve requests served with continuous batching: one JSON line."""
+    st = run_serve(args, args.serve_requests, args.serve_rate, args.serve_deadline_s)
+    span = st["serving"]["span_s"]
+    out = {
+        "metric": "served solves/s", "value": st["serving"]["done"] / span, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.serve_requests, "warmup": 0, "ms_per_step": 1e3 * span / max(1, st["serving"]["done"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-refinement",
+        "data": "synthetic", "config": st["config"], "serving": st["serving"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args, nreq, rate, deadline_s):
+    """Poisson stream of `nreq` solve requests at `rate` per second on the seven
+    meshes and three kernels of the serving workload, served with continuous
+    batching; returns the configuration and the service statistics."""
     import numpy as np
     import torch
 
@@ -378,8 +473,8 @@ def bench_serve(args):
     meshes.update({"cube%d" % N: I.cube_surface(N) for N in (32, 64, 128)})
     kernels = [("laplace", 0.0), ("helmholtz", 2.0), ("helmholtz", 4.0)]
     S = H2Server(GPUBackend(order=4, leaf=64, eta=0.5, storage="f32", coupling_otf=not args.no_otf),
-                 mem_budget=args.serve_budget_gb * 1e9,
-                 max_active=args.serve_slots)
+                 mem_budget=args.serve_budget_gb * 1e9, max_active=args.serve_slots,
+                 vec_budget=args.serve_vec_gb * 1e9)
     for name, (V, T) in meshes.items():
         S.register_mesh(name, V, T)
     t0 = time.perf_counter()
@@ -391,10 +486,10 @@ def bench_serve(args):
     log("serve: %d structures resident, %.1f GB, built in %.1f s" % (len(S.resident), S.used_bytes() / 1e9, build_s))
     rng = np.random.default_rng(5)
     names = sorted(meshes)
-    gaps = rng.exponential(1.0 / args.serve_rate, args.serve_requests)
+    gaps = rng.exponential(1.0 / rate, nreq)
     arrivals = np.cumsum(gaps)
     reqs_spec = []
-    for i in range(args.serve_requests):
+    for i in range(nreq):
         name = names[rng.integers(len(names))]
         kern, kap = kernels[rng.integers(3)]
         r = int(rng.integers(1, 17))
@@ -410,30 +505,34 @@ def bench_serve(args):
     for (name, kern, kap, B), a in zip(reqs_spec, arrivals):
         S.submit(name, B, kernel=kern, kappa=kap, rtol=1e-8, arrival=start + a)
     S.run(progress=lambda d: log("serve progress:", json.dumps(d)), progress_every=10.0,
-          deadline=start + args.serve_deadline_s)
+          deadline=start + deadline_s)
     torch.cuda.synchronize()
     st = S.stats()
     span = max(q.finish for q in S.finished) - start
-    out = {
-        "metric": "served solves/s", "value": st["done"] / span, "unit": "solves/s", "n_gpus": 1,
-        "steps": args.serve_requests, "warmup": 0, "ms_per_step": 1e3 * span / max(1, st["done"]),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-refinement",
-        "data": "synthetic",
+    done = [q for q in S.finished if q.status == "done"]
+    res = {
         "config": {"workload": "serve_mix", "meshes": {k: int(v[1].shape[0]) for k, v in meshes.items()},
                    "kernels": ["laplace", "helmholtz k=2", "helmholtz k=4"], "rhs": "U{1..16}",
-                   "arrival_rate_per_s": args.serve_rate, "rtol": 1e-8, "slots": args.serve_slots,
+                   "requests": nreq, "arrival_rate_per_s": rate, "rtol": 1e-8, "slots": args.serve_slots,
                    "storage": "f32 (FP64 iterative refinement)",
-                   "laplace_coupling": "stored" if args.no_otf else "evaluated during the product"},
+                   "coupling": "stored" if args.no_otf else "evaluated during the product"},
         "serving": dict(st, build_s=build_s, span_s=span, resident_GB=S.used_bytes() / 1e9,
+                        solves_per_s=len(done) / span if span > 0 else None,
+                        rhs_per_s=sum(q.nrhs for q in done) / span if span > 0 else None,
                         failures=S.failures()[:20],
                         iterations_mean=float(np.mean([q.iterations for q in S.finished])),
                         iterations_by_kernel={k: float(np.mean([q.iterations for q in S.finished if q.kernel == k]))
                                               for k in ("laplace", "helmholtz")},
-                        latency_p50_by_kernel={k: float(np.percentile([q.latency for q in S.finished
-                                                                       if q.kernel == k and q.status == "done"], 50))
-                                               for k in ("laplace", "helmholtz")}),
+                        latency_p50_by_kernel={k: float(np.percentile([q.latency for q in done if q.kernel == k], 50))
+                                               for k in ("laplace", "helmholtz")
+                                               if any(q.kernel == k for q in done)}),
     }
-    print(json.dumps(out), flush=True)
+    for res_ in S.resident.values():
+        S.be.free(res_.obj)
+    del S
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -448,8 +547,15 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-budget-gb", type=float, default=220.0)
+    ap.add_argument("--serve-vec-gb", type=float, default=40.0, help="request vector arena of the service")
     ap.add_argument("--serve-deadline-s", type=float, default=150.0, help="cancel what is unfinished after this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-child", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--n-adm", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--n-near", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-cores", type=int, default=0, help="host cores for the all-core oracle baseline "
+                    "(default: all this process may use, at most 16)")
     ap.add_argument("--recompress", type=float, default=1e-5, metavar="EPS",
                     help="tolerance of the algebraically recompressed variant (default 1e-5)")
     ap.add_argument("--no-recompress", dest="recompress", action="store_const", const=None,
@@ -459,9 +565,17 @@ def main():
     ap.add_argument("--no-solve", "--no-fp64", dest="no_solve", action="store_true",
                     help="skip the solve comparison (FP64 vs mixed precision vs BF16 coupling)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a device copy of known size")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the read-only streaming kernel")
+    ap.add_argument("--no-multi", action="store_true", help="skip the 64-column leg of the default run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the default run")
+    ap.add_argument("--bench-serve-requests", type=int, default=100)
+    ap.add_argument("--bench-serve-rate", type=float, default=2.0)
+    ap.add_argument("--bench-serve-deadline-s", type=float, default=100.0)
     ap.add_argument("--no-otf", action="store_true",
                     help="skip the variant with coupling matrices evaluated during the product")
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        return cpu_baseline_child(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the H^2 product here runs on a single MI355X "
               "(multi-GPU sharding is not implemented); use --gpus 1", file=sys.stderr)
@@ -625,12 +739,32 @@ def main():
                                    "time_to_1e-8_mixed_s": solves[storage]["seconds"]}
     if args.copy_probe:
         out["copy_probe"] = copy_probe(torch)
+    if not args.no_ceiling:
+        log("bench: read ceiling")
+        ceil = read_ceiling(torch, h2)
+        roof = out["roofline"]
+        roof["measured_ceiling"] = ceil["GBs"] if roof["unit"] == "GB/s" else None
+        roof["frac_of_measured_ceiling"] = roof["achieved"] / ceil["GBs"] if roof["unit"] == "GB/s" else None
+        out["read_ceiling"] = ceil
+    headline = args.workload == "sphere1310k_m4_f32"
+    if headline and not args.no_multi:
+        log("bench: many right-hand sides (cube786k, 64 columns)")
+        mr = run_multi(args, "cube786k_m4_r64", full=False)
+        out["multi_rhs"] = {k: mr[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "roofline", "path",
+                                               "tuning", "graph_replay")}
+    if headline and not args.no_serve:
+        log("bench: serving leg (%d requests at %.1f/s)" % (args.bench_serve_requests, args.bench_serve_rate))
+        out["serving"] = run_serve(args, args.bench_serve_requests, args.bench_serve_rate, args.bench_serve_deadline_s)
     if not args.no_cpu_baseline:
-        log("bench: CPU oracle sample")
+        wl = OTF_WORKLOADS.get(args.workload, args.workload)
+        cores = args.cpu_cores or min(16, host_cores())
         try:
-            from threadpoolctl import threadpool_limits
-            with threadpool_limits(limits=1):
-                out["cpu_baseline"] = cpu_baseline_sample(kind, level, order, leaf, seed)
+            log("bench: CPU oracle sample, %d cores" % cores)
+            allc = cpu_baseline(args, wl, info["n_adm"], info["n_near"], cores, 12.0)
+            log("bench: CPU oracle sample, 1 core")
+            one = cpu_baseline(args, wl, info["n_adm"], info["n_near"], 1, 20.0)
+            allc["one_core"] = one
+            out["cpu_baseline"] = allc
         except Exception as e:  # the baseline is a report, never a reason to lose the line
             out["cpu_baseline"] = {"value": None, "error": repr(e)}
     print(json.dumps(out), flush=True)

@@ -368,6 +368,15 @@ int h2_krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, in
                      int64_t q_vec_stride, const void* h, double sign, void* W, int64_t w_rhs_stride,
                      void* stream);
 
+/* Measurement utility: reads `bytes` (a positive multiple of 16) of DEVICE memory
+ * at `data` (16-byte aligned) with 16-byte non-temporal loads, four in flight per
+ * thread, the way the bandwidth-bound product kernels stream their data, and
+ * writes nothing in practice (`sink`, DEVICE memory of at least
+ * 4 * min(8192, ceil(bytes / 16384)) bytes, keeps the loads live).  Timed by the
+ * caller; bytes / time is the HBM read rate a plain kernel reaches, the measured
+ * ceiling beside the vendor peak.  Asynchronous on `stream`. */
+int h2_stream_read(const void* data, int64_t bytes, void* sink, int64_t sink_bytes, void* stream);
+
 /* Per-phase device timing of h2_matvec (HIP events on the call's stream).
  * h2_profile(h, 1) enables and clears; h2_profile(h, 0) disables.
  * h2_profile_read fills ms[H2_NPHASE] with summed milliseconds and

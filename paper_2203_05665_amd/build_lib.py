@@ -21,7 +21,7 @@ ARCH = os.environ.get("H2_OFFLOAD_ARCH", "gfx950")
 
 HOST_SOURCES = ["structure.cpp", "quadrules.cpp"]
 HIP_SOURCES = ["assemble.hip", "matvec.hip", "matvec_multi.hip", "ksolve.hip", "krylov.hip", "recompress.hip",
-               "tune.hip", "capi.hip"]
+               "tune.hip", "probe.hip", "capi.hip"]
 
 
 def _hipcc():
@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
     for s in HOST_SOURCES:
         o = os.path.join(BUILD, s + ".o")
         objs.append(o)
-        jobs.append(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-c",
+        jobs.append(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall", "-c",
                      os.path.join(CSRC, s), "-o", o])
     for s in HIP_SOURCES:
         o = os.path.join(BUILD, s + ".o")
@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout, r.stderr)
     tmp = OUT + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs)
+    _run([hipcc, "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-o", tmp] + objs)
     os.replace(tmp, OUT)
     return OUT
 

@@ -12,6 +12,9 @@
 // the x-triangle, so g_ij and g_ji are computed identically.
 #include <hip/hip_runtime.h>
 
+#include <functional>
+#include <string>
+#include <thread>
 #include <type_traits>
 
 #include <algorithm>
@@ -489,46 +492,76 @@ void assemble_typed(h2_handle_s& H) {
       for (int a = 0; a < 3; ++a) vt[fill[S.tri[3 * t + a]]++] = static_cast<int32_t>(t);
     std::vector<int32_t> inv(n);
     for (int64_t p = 0; p < n; ++p) inv[S.perm[p]] = static_cast<int32_t>(p);
+    // the touching pairs of positions [p0, p1), one list per Sauter-Schwab case;
+    // chunks of positions run on separate threads and their lists are joined in
+    // position order
+    struct Lists {
+      std::vector<int64_t> dst[3];
+      std::vector<int32_t> ta[3], tb[3];
+      std::string err;
+    };
+    auto scan = [&](int64_t p0, int64_t p1, Lists& L) {
+      std::vector<int32_t> nb;
+      for (int64_t p = p0; p < p1; ++p) {
+        const int32_t t = S.perm[p];
+        nb.clear();
+        for (int a = 0; a < 3; ++a) {
+          const int32_t v = S.tri[3 * static_cast<int64_t>(t) + a];
+          for (int64_t q = vptr[v]; q < vptr[v + 1]; ++q) nb.push_back(vt[q]);
+        }
+        std::sort(nb.begin(), nb.end());
+        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        const int32_t l = S.leaf_of_pos[p];
+        const int32_t tau = S.leaves[l];
+        const int64_t r = S.cend[tau] - S.cbegin[tau];
+        for (int32_t t2 : nb) {
+          const int32_t q = inv[t2];
+          // symmetric storage keeps the pair in the block of the earlier leaf only
+          if (S.sym_n && S.leaf_of_pos[q] < l) continue;
+          const int32_t sc = S.leaves[S.leaf_of_pos[q]];
+          // the near block (l, sc): columns of row l are sorted by cluster start
+          const int64_t lo = S.near_ptr[l], hi = S.near_ptr[l + 1];
+          const int32_t* beg = S.near_col.data();
+          int64_t a0 = lo, a1 = hi;
+          while (a0 < a1) {
+            const int64_t mid = (a0 + a1) / 2;
+            if (S.cbegin[beg[mid]] < S.cbegin[sc]) a0 = mid + 1; else a1 = mid;
+          }
+          if (!(a0 < hi && beg[a0] == sc)) {
+            L.err = "touching pair outside the near field";
+            return;
+          }
+          int shared = 0;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              shared += S.tri[3 * static_cast<int64_t>(t) + i] == S.tri[3 * static_cast<int64_t>(t2) + j];
+          const int c = (t == t2) ? SS_IDENTICAL : (shared >= 2 ? SS_EDGE : SS_VERTEX);
+          L.dst[c].push_back(S.panel_off[l] + (static_cast<int64_t>(cs[a0]) + (q - S.cbegin[sc])) * r +
+                             (p - S.cbegin[tau]));
+          L.ta[c].push_back(std::min(t, t2));
+          L.tb[c].push_back(std::max(t, t2));
+        }
+      }
+    };
+    const int64_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int nth = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(hw, n / 8192)));
+    std::vector<Lists> lists(nth);
+    {
+      std::vector<std::thread> pool;
+      for (int w = 1; w < nth; ++w) pool.emplace_back(scan, n * w / nth, n * (w + 1) / nth, std::ref(lists[w]));
+      scan(0, n / nth, lists[0]);
+      for (auto& th : pool) th.join();
+    }
+    for (const Lists& L : lists)
+      if (!L.err.empty()) throw Error(H2_EINTERNAL, L.err);
     std::vector<int64_t> dst[3];
     std::vector<int32_t> ta[3], tb[3];
-    std::vector<int32_t> nb;
-    for (int64_t p = 0; p < n; ++p) {
-      const int32_t t = S.perm[p];
-      nb.clear();
-      for (int a = 0; a < 3; ++a) {
-        const int32_t v = S.tri[3 * static_cast<int64_t>(t) + a];
-        for (int64_t q = vptr[v]; q < vptr[v + 1]; ++q) nb.push_back(vt[q]);
+    for (int c = 0; c < 3; ++c)
+      for (const Lists& L : lists) {
+        dst[c].insert(dst[c].end(), L.dst[c].begin(), L.dst[c].end());
+        ta[c].insert(ta[c].end(), L.ta[c].begin(), L.ta[c].end());
+        tb[c].insert(tb[c].end(), L.tb[c].begin(), L.tb[c].end());
       }
-      std::sort(nb.begin(), nb.end());
-      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-      const int32_t l = S.leaf_of_pos[p];
-      const int32_t tau = S.leaves[l];
-      const int64_t r = S.cend[tau] - S.cbegin[tau];
-      for (int32_t t2 : nb) {
-        const int32_t q = inv[t2];
-        // symmetric storage keeps the pair in the block of the earlier leaf only
-        if (S.sym_n && S.leaf_of_pos[q] < l) continue;
-        const int32_t sc = S.leaves[S.leaf_of_pos[q]];
-        // the near block (l, sc): columns of row l are sorted by cluster start
-        const int64_t lo = S.near_ptr[l], hi = S.near_ptr[l + 1];
-        const int32_t* beg = S.near_col.data();
-        int64_t f = -1;
-        int64_t a0 = lo, a1 = hi;
-        while (a0 < a1) {
-          const int64_t mid = (a0 + a1) / 2;
-          if (S.cbegin[beg[mid]] < S.cbegin[sc]) a0 = mid + 1; else a1 = mid;
-        }
-        if (a0 < hi && beg[a0] == sc) f = a0;
-        if (f < 0) throw Error(H2_EINTERNAL, "touching pair outside the near field");
-        int shared = 0;
-        for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) shared += S.tri[3 * static_cast<int64_t>(t) + i] == S.tri[3 * static_cast<int64_t>(t2) + j];
-        const int c = (t == t2) ? SS_IDENTICAL : (shared >= 2 ? SS_EDGE : SS_VERTEX);
-        dst[c].push_back(S.panel_off[l] + (static_cast<int64_t>(cs[f]) + (q - S.cbegin[sc])) * r + (p - S.cbegin[tau]));
-        ta[c].push_back(std::min(t, t2));
-        tb[c].push_back(std::max(t, t2));
-      }
-    }
     SSArgs sa{};
     sa.vert = vert.as<double>();
     sa.tri = tri.as<int32_t>();

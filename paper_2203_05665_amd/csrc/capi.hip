@@ -483,6 +483,13 @@ int h2_krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, in
   });
 }
 
+int h2_stream_read(const void* data, int64_t bytes, void* sink, int64_t sink_bytes, void* stream) {
+  return guarded([&]() -> int {
+    h2::stream_read_launch(data, bytes, sink, sink_bytes, static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
 int h2_profile(h2_handle h, int enable) {
   return guarded([&]() -> int {
     if (!h) return fail(H2_EINVAL, "NULL handle");

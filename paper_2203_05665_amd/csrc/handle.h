@@ -128,6 +128,7 @@ void krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int6
 void recompress(h2_handle_s& H, double eps, int max_rank, h2_recompress_info& info, hipStream_t st);
 void tune(h2_handle_s& H, int nrhs, int dtype, int reps, h2_tune_info& info, hipStream_t st);
 void set_tuning(h2_handle_s& H, int knob, int value);
+void stream_read_launch(const void* data, int64_t bytes, void* sink, int64_t sink_bytes, hipStream_t st);
 hipEvent_t prof_event(h2_handle_s& H);
 void prof_record(h2_handle_s& H, int phase, hipEvent_t a, hipEvent_t b);
 }  // namespace h2

@@ -305,12 +305,10 @@ __global__ __launch_bounds__(64) void k_finish(Geo g, int op, int nvec, int j, c
   const int64_t e1 = e0 + (g).csz < (g).n ? e0 + (g).csz : (g).n;         \
   for (int64_t e = e0 + threadIdx.x; e < e1; e += KT)
 
-// D = S (columns with offsets d_col / s_col), or 0 when zero is set
-__global__ __launch_bounds__(KT) void k_copy(Geo g, const double* __restrict__ S, int64_t s_col, double* __restrict__ D,
-                                             int64_t d_col, int zero) {
+// D = 0 (columns d_col apart)
+__global__ __launch_bounds__(KT) void k_zero(Geo g, double* __restrict__ D, int64_t d_col) {
   CHUNK_LOOP(g) {
-    for (int q = 0; q < g.cw; ++q)
-      D[c * d_col + g.cw * e + q] = zero ? 0.0 : S[c * s_col + g.cw * e + q];
+    for (int q = 0; q < g.cw; ++q) D[c * d_col + g.cw * e + q] = 0.0;
   }
 }
 
@@ -683,7 +681,7 @@ void KSolver::begin(const void* b, int64_t ldb, const void* z0, int64_t ldz, hip
     pend_inner = pend_close = pend_zupd = false;
   } else {
     // Z = 0: the outer residual is B itself, relative residual 1 (0 for b_c = 0)
-    k_copy<<<grid, KT, 0, st>>>(g, nullptr, 0, d(L.off_Z), L.col, 1);
+    k_zero<<<grid, KT, 0, st>>>(g, d(L.off_Z), L.col);
     rhs = B;
     rhs_col = b_col;
     ++outer;
@@ -720,7 +718,7 @@ int KSolver::next(void* x, int64_t ldx, int* flags, hipStream_t st) {
       k_cg_init<<<grid, KT, 0, st>>>(g, rhs, rhs_col, d(L.off_X), d(L.off_R), d(L.off_P), col, d(L.off_part));
       finish(OP_CG_INIT, 1, 0, st);
     } else {
-      k_copy<<<grid, KT, 0, st>>>(g, nullptr, 0, d(L.off_X), col, 1);
+      k_zero<<<grid, KT, 0, st>>>(g, d(L.off_X), col);
       partial(1, rhs, rhs_col, 0, rhs, rhs_col, st);
       finish(OP_GM_START, 1, 0, st);
       k_scale<<<grid, KT, 0, st>>>(g, rhs, rhs_col, d(L.off_Q), qcol, d(L.off_scal));
@@ -780,6 +778,8 @@ void KSolver::advance(const void* y, int64_t ldy, hipStream_t st) {
       ++iterations;
       break;
     case PH_ARNOLDI: {
+      // the cycle holds at most m steps: poll() closes it before a step would overrun Q
+      if (j >= L.m) throw Error(H2_EINVAL, "h2_krylov_poll must follow every advance");
       // classical Gram-Schmidt, twice: h = Q^H y, w = y - Q h; h' = Q^H w, w -= Q h'
       const double* Q = d(L.off_Q);
       double* W = d(L.off_W);

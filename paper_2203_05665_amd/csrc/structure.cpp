@@ -8,6 +8,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <thread>
 
 namespace h2 {
 namespace {
@@ -17,17 +18,46 @@ struct Node {
   double lo[3], hi[3];
 };
 
+// Work below this many triangles (tree) or pairs (block tree) stays on the
+// calling thread; above it the two halves of a split run on two threads.
+constexpr int32_t kParallelTriangles = 1 << 15;
+
+int worker_threads() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return static_cast<int>(std::max(1u, std::min(16u, h)));
+}
+
+// runs f(i) for i in [0, n) on up to `threads` threads, in contiguous chunks
+template <class F>
+void parallel_for(int64_t n, int threads, F&& f) {
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(threads, n / 4096));
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int64_t w = 0; w < nt; ++w)
+    pool.emplace_back([&, w]() {
+      for (int64_t i = n * w / nt; i < n * (w + 1) / nt; ++i) f(i);
+    });
+  for (auto& t : pool) t.join();
+}
+
 struct TreeBuilder {
   const double* V;
   const int32_t* T;
   int leaf;
   std::vector<int32_t> idx, tmp;
   std::vector<double> cen;  // n x 3
-  std::vector<Node> nodes;  // depth-first pre-order
 
-  int32_t build(int32_t begin, int32_t end, int32_t level, int32_t parent) {
-    const int32_t id = static_cast<int32_t>(nodes.size());
-    nodes.push_back(Node{begin, end, level, parent, {-1, -1}, {0, 0, 0}, {0, 0, 0}});
+  // Builds the subtree of idx[begin, end) into `out` in depth-first pre-order
+  // (child 0 before child 1) and returns the position of its root in `out`.
+  // The index ranges of two children are disjoint, so with par_depth > 0 the
+  // subtree of child 0 is built on a second thread into a vector of its own and
+  // both are appended in pre-order afterwards: the same tree, node for node.
+  int32_t build(std::vector<Node>& out, int32_t begin, int32_t end, int32_t level, int32_t parent, int par_depth) {
+    const int32_t id = static_cast<int32_t>(out.size());
+    out.push_back(Node{begin, end, level, parent, {-1, -1}, {0, 0, 0}, {0, 0, 0}});
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int32_t p = begin; p < end; ++p) {
       const int32_t t = idx[p];
@@ -40,8 +70,8 @@ struct TreeBuilder {
       }
     }
     for (int d = 0; d < 3; ++d) {
-      nodes[id].lo[d] = lo[d];
-      nodes[id].hi[d] = hi[d];
+      out[id].lo[d] = lo[d];
+      out[id].hi[d] = hi[d];
     }
     const int32_t size = end - begin;
     if (size <= leaf) return id;
@@ -70,11 +100,33 @@ struct TreeBuilder {
       if (cen[3 * static_cast<int64_t>(t) + axis] < mid) tmp[a++] = t; else tmp[b++] = t;
     }
     std::copy(tmp.begin() + begin, tmp.begin() + end, idx.begin() + begin);
-    const int32_t c0 = build(begin, begin + nlow, level + 1, id);
-    const int32_t c1 = build(begin + nlow, end, level + 1, id);
-    nodes[id].child[0] = c0;
-    nodes[id].child[1] = c1;
+    int32_t c0, c1;
+    if (par_depth > 0 && size >= kParallelTriangles) {
+      std::vector<Node> v0, v1;
+      std::thread th([&]() { build(v0, begin, begin + nlow, level + 1, -1, par_depth - 1); });
+      build(v1, begin + nlow, end, level + 1, -1, par_depth - 1);
+      th.join();
+      c0 = append(out, v0, id);
+      c1 = append(out, v1, id);
+    } else {
+      c0 = build(out, begin, begin + nlow, level + 1, id, 0);
+      c1 = build(out, begin + nlow, end, level + 1, id, 0);
+    }
+    out[id].child[0] = c0;
+    out[id].child[1] = c1;
     return id;
+  }
+
+  // appends a subtree built on its own (local positions, root parent -1)
+  static int32_t append(std::vector<Node>& out, const std::vector<Node>& v, int32_t parent) {
+    const int32_t off = static_cast<int32_t>(out.size());
+    for (Node nd : v) {
+      nd.parent = nd.parent < 0 ? parent : nd.parent + off;
+      for (int c = 0; c < 2; ++c)
+        if (nd.child[c] >= 0) nd.child[c] += off;
+      out.push_back(nd);
+    }
+    return off;
   }
 };
 
@@ -95,15 +147,18 @@ inline double dist(const Structure& S, int32_t t, int32_t s) {
   return std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
 }
 
+using Pairs = std::vector<std::pair<int32_t, int32_t>>;
+
 struct BlockBuilder {
   const Structure& S;
   std::vector<double> dia;
-  std::vector<std::pair<int32_t, int32_t>> adm, near;
   explicit BlockBuilder(const Structure& s) : S(s) {
     dia.resize(S.nclusters);
     for (int32_t c = 0; c < S.nclusters; ++c) dia[c] = diam(S, c);
   }
-  void visit(int32_t t, int32_t s) {
+  // one step of the block tree for the pair (t, s): an admissible leaf, an
+  // inadmissible leaf, or its children pairs appended to `next`
+  void step(int32_t t, int32_t s, Pairs& adm, Pairs& near, Pairs& next) const {
     const double lhs = std::max(dia[t], dia[s]);
     if (lhs <= 2.0 * S.eta * dist(S, t, s)) {
       adm.emplace_back(t, s);
@@ -111,21 +166,73 @@ struct BlockBuilder {
     }
     const bool ct = S.child0[t] >= 0, cs = S.child0[s] >= 0;
     if (ct && cs) {
-      visit(S.child0[t], S.child0[s]);
-      visit(S.child0[t], S.child1[s]);
-      visit(S.child1[t], S.child0[s]);
-      visit(S.child1[t], S.child1[s]);
+      next.emplace_back(S.child0[t], S.child0[s]);
+      next.emplace_back(S.child0[t], S.child1[s]);
+      next.emplace_back(S.child1[t], S.child0[s]);
+      next.emplace_back(S.child1[t], S.child1[s]);
     } else if (cs) {
-      visit(t, S.child0[s]);
-      visit(t, S.child1[s]);
+      next.emplace_back(t, S.child0[s]);
+      next.emplace_back(t, S.child1[s]);
     } else if (ct) {
-      visit(S.child0[t], s);
-      visit(S.child1[t], s);
+      next.emplace_back(S.child0[t], s);
+      next.emplace_back(S.child1[t], s);
     } else {
       near.emplace_back(t, s);
     }
   }
+  void visit(int32_t t, int32_t s, Pairs& adm, Pairs& near) const {
+    Pairs stack{{t, s}}, next;
+    while (!stack.empty()) {
+      const auto pr = stack.back();
+      stack.pop_back();
+      next.clear();
+      step(pr.first, pr.second, adm, near, next);
+      stack.insert(stack.end(), next.rbegin(), next.rend());
+    }
+  }
+  // The leaves of the block tree of (root, root).  The top of the tree is
+  // expanded breadth first until there is work for every thread; each thread then
+  // visits a contiguous share of the pending pairs.  The leaves are sorted by the
+  // caller, so the result does not depend on the order they were found in.
+  void build(int threads, Pairs& adm, Pairs& near) const {
+    Pairs front{{0, 0}}, next;
+    while (!front.empty() && front.size() < static_cast<size_t>(64 * threads)) {
+      next.clear();
+      for (const auto& pr : front) step(pr.first, pr.second, adm, near, next);
+      front.swap(next);
+    }
+    const int nt = static_cast<int>(std::min<size_t>(threads, front.size()));
+    if (nt <= 1) {
+      for (const auto& pr : front) visit(pr.first, pr.second, adm, near);
+      return;
+    }
+    std::vector<Pairs> ta(nt), tn(nt);
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nt; ++w)
+      pool.emplace_back([&, w]() {
+        for (size_t i = front.size() * w / nt; i < front.size() * (w + 1) / nt; ++i)
+          visit(front[i].first, front[i].second, ta[w], tn[w]);
+      });
+    for (auto& th : pool) th.join();
+    for (int w = 0; w < nt; ++w) {
+      adm.insert(adm.end(), ta[w].begin(), ta[w].end());
+      near.insert(near.end(), tn[w].begin(), tn[w].end());
+    }
+  }
 };
+
+// CSR by row of a list of pairs: ptr[nrows + 1]; columns of a row in the order
+// `less` gives (a counting sort by row, then each row's few columns sorted)
+template <class Less>
+void csr_by_row(const Pairs& pairs, int32_t nrows, std::vector<int64_t>& ptr, std::vector<int32_t>& col, Less less) {
+  ptr.assign(nrows + 1, 0);
+  for (const auto& pr : pairs) ptr[pr.first + 1]++;
+  for (int32_t i = 0; i < nrows; ++i) ptr[i + 1] += ptr[i];
+  col.resize(pairs.size());
+  std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+  for (const auto& pr : pairs) col[fill[pr.first]++] = pr.second;
+  for (int32_t i = 0; i < nrows; ++i) std::sort(col.begin() + ptr[i], col.begin() + ptr[i + 1], less);
+}
 
 }  // namespace
 
@@ -147,30 +254,34 @@ void build_structure(Structure& S, const double* vertices, int64_t nv, const int
   S.vert.assign(vertices, vertices + 3 * nv);
   S.tri.assign(triangles, triangles + 3 * nt);
 
-  TreeBuilder tb{S.vert.data(), S.tri.data(), leaf_size, {}, {}, {}, {}};
+  const int threads = worker_threads();
+  TreeBuilder tb{S.vert.data(), S.tri.data(), leaf_size, {}, {}, {}};
   tb.idx.resize(nt);
   tb.tmp.resize(nt);
   std::iota(tb.idx.begin(), tb.idx.end(), 0);
   tb.cen.resize(3 * nt);
-  for (int64_t t = 0; t < nt; ++t) {
+  parallel_for(nt, threads, [&](int64_t t) {
     const double* p0 = &S.vert[3 * static_cast<int64_t>(S.tri[3 * t])];
     const double* p1 = &S.vert[3 * static_cast<int64_t>(S.tri[3 * t + 1])];
     const double* p2 = &S.vert[3 * static_cast<int64_t>(S.tri[3 * t + 2])];
     for (int d = 0; d < 3; ++d) tb.cen[3 * t + d] = (p0[d] + p1[d] + p2[d]) / 3.0;
-  }
-  tb.build(0, static_cast<int32_t>(nt), 0, -1);
+  });
+  std::vector<Node> nodes;
+  int par_depth = 0;
+  while ((1 << par_depth) < threads) ++par_depth;
+  tb.build(nodes, 0, static_cast<int32_t>(nt), 0, -1, par_depth);
   S.perm = tb.idx;
 
   // renumber breadth first (stable within a level = depth-first order)
-  const int32_t nc = static_cast<int32_t>(tb.nodes.size());
+  const int32_t nc = static_cast<int32_t>(nodes.size());
   S.nclusters = nc;
   int32_t depth = 0;
-  for (const Node& nd : tb.nodes) depth = std::max(depth, nd.level);
+  for (const Node& nd : nodes) depth = std::max(depth, nd.level);
   S.depth = depth;
   std::vector<int32_t> order(nc);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return tb.nodes[a].level < tb.nodes[b].level; });
+                   [&](int32_t a, int32_t b) { return nodes[a].level < nodes[b].level; });
   std::vector<int32_t> newid(nc);
   for (int32_t i = 0; i < nc; ++i) newid[order[i]] = i;
   S.cbegin.resize(nc); S.cend.resize(nc); S.parent.resize(nc); S.child0.resize(nc);
@@ -178,7 +289,7 @@ void build_structure(Structure& S, const double* vertices, int64_t nv, const int
   S.lo.resize(3 * nc); S.hi.resize(3 * nc);
   S.level_ptr.assign(depth + 2, 0);
   for (int32_t i = 0; i < nc; ++i) {
-    const Node& nd = tb.nodes[order[i]];
+    const Node& nd = nodes[order[i]];
     S.cbegin[i] = nd.begin;
     S.cend[i] = nd.end;
     S.parent[i] = nd.parent >= 0 ? newid[nd.parent] : -1;
@@ -202,35 +313,19 @@ void build_structure(Structure& S, const double* vertices, int64_t nv, const int
   for (size_t l = 0; l < S.leaves.size(); ++l)
     for (int32_t p = S.cbegin[S.leaves[l]]; p < S.cend[S.leaves[l]]; ++p) S.leaf_of_pos[p] = static_cast<int32_t>(l);
 
-  // block tree
+  // block tree: admissible leaves by row cluster, columns ascending; inadmissible
+  // leaves by row leaf, columns by their first position
   BlockBuilder bb(S);
-  bb.visit(0, 0);
-  auto by_row = [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
-    return a.first != b.first ? a.first < b.first : a.second < b.second;
-  };
-  std::sort(bb.adm.begin(), bb.adm.end(), by_row);
-  S.adm_ptr.assign(nc + 1, 0);
-  S.adm_col.resize(bb.adm.size());
-  for (size_t b = 0; b < bb.adm.size(); ++b) {
-    S.adm_ptr[bb.adm[b].first + 1]++;
-    S.adm_col[b] = bb.adm[b].second;
-  }
-  for (int32_t i = 0; i < nc; ++i) S.adm_ptr[i + 1] += S.adm_ptr[i];
+  Pairs adm, near;
+  bb.build(threads, adm, near);
+  csr_by_row(adm, nc, S.adm_ptr, S.adm_col, [](int32_t a, int32_t b) { return a < b; });
 
   const int32_t nl = static_cast<int32_t>(S.leaves.size());
   std::vector<int32_t> leaf_index(nc, -1);
   for (int32_t l = 0; l < nl; ++l) leaf_index[S.leaves[l]] = l;
-  for (auto& pr : bb.near) pr.first = leaf_index[pr.first];
-  std::sort(bb.near.begin(), bb.near.end(), [&](const auto& a, const auto& b) {
-    return a.first != b.first ? a.first < b.first : S.cbegin[a.second] < S.cbegin[b.second];
-  });
-  S.near_ptr.assign(nl + 1, 0);
-  S.near_col.resize(bb.near.size());
-  for (size_t b = 0; b < bb.near.size(); ++b) {
-    S.near_ptr[bb.near[b].first + 1]++;
-    S.near_col[b] = bb.near[b].second;
-  }
-  for (int32_t l = 0; l < nl; ++l) S.near_ptr[l + 1] += S.near_ptr[l];
+  for (auto& pr : near) pr.first = leaf_index[pr.first];
+  csr_by_row(near, nl, S.near_ptr, S.near_col,
+             [&](int32_t a, int32_t b) { return S.cbegin[a] < S.cbegin[b]; });
   S.panel_off.assign(nl + 1, 0);
   for (int32_t l = 0; l < nl; ++l) {
     const int64_t r = S.cend[S.leaves[l]] - S.cbegin[S.leaves[l]];

@@ -108,6 +108,7 @@ def lib():
         L.h2_krylov_solution.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.h2_krylov_destroy.argtypes = [C.c_void_p]
         L.h2_krylov_destroy.restype = None
+        L.h2_stream_read.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
         L.h2_info.argtypes = [C.c_void_p, C.POINTER(h2_stats)]
         L.h2_free.argtypes = [C.c_void_p]
         L.h2_free.restype = None
@@ -125,7 +126,7 @@ def lib():
         for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
                   "h2_krylov_dots", "h2_krylov_update", "h2_recompress", "h2_tune", "h2_set_tuning",
                   "h2_krylov_create", "h2_krylov_begin", "h2_krylov_next", "h2_krylov_advance", "h2_krylov_poll",
-                  "h2_krylov_residuals", "h2_krylov_solution"):
+                  "h2_krylov_residuals", "h2_krylov_solution", "h2_stream_read"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -348,6 +349,13 @@ def h2_krylov_update(Q, h, W, sign=1.0, stream=None):
     _check(lib().h2_krylov_update(_kdtype(Q), r, nvec, n, Q.data_ptr(), Q.stride(0), Q.stride(1), h.data_ptr(),
                                   float(sign), W.data_ptr(), W.stride(0), _stream(stream)))
     return W
+
+
+def h2_stream_read(buf, sink, stream=None):
+    """Launch the read-only streaming kernel over the bytes of device tensor `buf`
+    (sink: a device tensor of at least 32 KiB)."""
+    _check(lib().h2_stream_read(buf.data_ptr(), buf.numel() * buf.element_size(), sink.data_ptr(),
+                                sink.numel() * sink.element_size(), _stream(stream)))
 
 
 def h2_recompress(h, eps, max_rank=0, stream=None) -> dict:

@@ -28,13 +28,18 @@ def test_recorded_traffic_matches_the_algorithmic_bytes():
     assert bench.recorded_traffic("no_such_workload") is None
 
 
-def test_cpu_baseline_sampler_on_a_small_mesh():
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        out = bench.cpu_baseline_sample("sphere", 4, 4, 64, 2, budget_s=1.0)
-    assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "H2 matvecs/s"
-    assert out["value"] > 0 and abs(out["value"] * out["est_seconds_per_matvec"] - 1.0) < 1e-12
-    assert "subtree" in out["sample"]
+def test_cpu_baseline_child_on_a_small_mesh():
+    """The oracle baseline runs in a child interpreter on one core and on two
+    (each core timing its own sample; their rates add)."""
+    class A:
+        workload = "sphere5120_m4_f64"
+    for cores in (1, 2):
+        out = bench.cpu_baseline(A, "sphere5120_m4_f64", 300000, 60000, cores, 1.0)
+        assert out["kind"] == "oracle" and out["cores"] == cores and out["unit"] == "H2 matvecs/s", out
+        est = out["est_seconds_per_matvec_per_core"]
+        assert len(est) == cores and out["value"] > 0
+        assert abs(out["value"] - sum(1.0 / e for e in est)) < 1e-9 * out["value"]
+        assert "subtree" in out["sample"]
 
 
 def test_profile_commands_run_committed_files_with_known_flags():

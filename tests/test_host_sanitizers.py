@@ -19,7 +19,7 @@ CSRC = os.path.join(ROOT, "paper_2203_05665_amd", "csrc")
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 def test_tree_code_under_address_and_ub_sanitizers(tmp_path):
     exe = str(tmp_path / "drive")
-    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
            "-fno-sanitize-recover=undefined", "-I", CSRC, os.path.join(ROOT, "tests", "host_sanitize_driver.cpp"),
            os.path.join(CSRC, "structure.cpp"), os.path.join(CSRC, "quadrules.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
