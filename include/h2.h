@@ -186,6 +186,24 @@ typedef struct {
 int h2_solve(h2_handle h, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
              const h2_solve_params* p, h2_solve_info* info, void* stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid allocation):
+ * h2_solve without any allocation.  The solver's workspace and its two
+ * n x nrhs product buffers live in a fixed device array of the library
+ * (H2_NOALLOC_SCRATCH_BYTES = 256 MiB per GPU, held from the library's load on
+ * that GPU until the process ends); the residual status is read into host stack
+ * memory; products with several columns use the many-right-hand-side path only
+ * if the handle already holds its workspaces (after an h2_matvec or h2_solve
+ * with as many columns), else they apply the columns one at a time.  H2_EINVAL
+ * when the solve needs more than the array (about (5 + restart) n nrhs FP64
+ * values plus 2 n nrhs for the products) or nrhs > H2_NOALLOC_MAX_RHS; otherwise
+ * as h2_solve.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other threads, other streams) race. */
+#define H2_NOALLOC_SCRATCH_BYTES (256ll << 20)
+#define H2_NOALLOC_MAX_RHS 64
+int h2_solve_noalloc(h2_handle h, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+                     const h2_solve_params* p, h2_solve_info* info, void* stream);
+
 /* Step-wise form of the same solver, for callers that batch the products of
  * several solves (the solve service issues one many-right-hand-side product
  * per matrix for all the solves that wait on it).  The solver never touches a

@@ -200,6 +200,18 @@ int h2_solve(h2_handle h, int nrhs, int dtype, const void* b, int64_t ldb, void*
   });
 }
 
+int h2_solve_noalloc(h2_handle h, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+                     const h2_solve_params* p, h2_solve_info* info, void* stream) {
+  return guarded([&]() -> int {
+    if (!h || !p) return fail(H2_EINVAL, "NULL argument");
+    h2_solve_info tmp{};
+    const int rc = h2::solve_noalloc(*h, nrhs, dtype, b, ldb, z, ldz, *p, info ? *info : tmp,
+                                     static_cast<hipStream_t>(stream));
+    if (rc == H2_ENOTCONV) return fail(rc, "solver did not reach the tolerance");
+    return rc;
+  });
+}
+
 int64_t h2_krylov_workspace(int dtype, int64_t n, int nrhs, const h2_solve_params* p) {
   try {
     if (!p || n < 1 || nrhs < 1 || (dtype != H2_R64 && dtype != H2_C128)) return -1;

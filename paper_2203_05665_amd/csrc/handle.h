@@ -114,13 +114,18 @@ struct h2_handle_s {
 
 namespace h2 {
 void assemble(h2_handle_s& H);  // fills Vf, Vb, F, ET, Smat, Nmat on the device
+// may_alloc = false: no device allocation; the many-RHS path is taken only when
+// its workspaces exist already, else the columns are applied one at a time
 void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
-            double alpha, int flags, hipStream_t s);
+            double alpha, int flags, hipStream_t s, bool may_alloc = true);
 bool matvec_multi_supported(const h2_handle_s& H);
+bool matvec_multi_ready(const h2_handle_s& H, int nrhs, int dtype);
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
                   double alpha, hipStream_t s);
 int solve_multi(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
                 const h2_solve_params& p, h2_solve_info& info, hipStream_t st);
+int solve_noalloc(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+                  const h2_solve_params& p, h2_solve_info& info, hipStream_t st);
 void krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* W,
                  int64_t wr, void* h, hipStream_t st);
 void krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* h,

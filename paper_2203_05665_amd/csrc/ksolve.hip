@@ -29,6 +29,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "handle.h"
@@ -310,6 +312,14 @@ __global__ __launch_bounds__(KT) void k_zero(Geo g, double* __restrict__ D, int6
   CHUNK_LOOP(g) {
     for (int q = 0; q < g.cw; ++q) D[c * d_col + g.cw * e + q] = 0.0;
   }
+}
+
+// p[0, count) = 0 (a kernel rather than a memset, so the solve records no memset node
+// if a caller captures its stream)
+__global__ __launch_bounds__(KT) void k_fill0(double* __restrict__ p, int64_t count) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * KT + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * KT)
+    p[i] = 0.0;
 }
 
 // Z = z0 for columns with b != 0, else 0
@@ -666,7 +676,10 @@ void KSolver::begin(const void* b, int64_t ldb, const void* z0, int64_t ldz, hip
   b_col = ldb * cw;
   const Geo g = geo_of(L);
   const dim3 grid(L.nchunk, L.r);
-  H2_HIP(hipMemsetAsync(d(L.off_scal), 0, static_cast<size_t>(L.r) * L.sc * 8, st));
+  {
+    const int64_t cnt = static_cast<int64_t>(L.r) * L.sc;
+    k_fill0<<<static_cast<unsigned>(std::min<int64_t>(1024, (cnt + KT - 1) / KT)), KT, 0, st>>>(d(L.off_scal), cnt);
+  }
   partial(1, B, b_col, 0, B, b_col, st);
   finish(OP_NB_OUT, 1, 0, st);
   iterations = outer = products = 0;
@@ -874,8 +887,9 @@ void KSolver::solution(void* z, int64_t ldz, hipStream_t st) {
 }
 
 // ============================================================================ h2_solve
-int solve_multi(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
-                const h2_solve_params& p, h2_solve_info& info, hipStream_t st) {
+namespace {
+void check_solve_args(const h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, const void* z,
+                      int64_t ldz, const h2_solve_params& p) {
   if (H.host_only) throw Error(H2_EINVAL, "handle was built with H2_HOST_ONLY");
   if (nrhs < 0) throw Error(H2_EINVAL, "nrhs must be >= 0");
   const bool cx = dtype == H2_C128;
@@ -884,39 +898,36 @@ int solve_multi(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb,
     throw Error(H2_EINVAL, H.is_complex ? "the Helmholtz matrix needs complex vectors (H2_C128)"
                                         : "complex vectors need the Helmholtz kernel");
   KSolver::check_params(p, cx);
-  info = h2_solve_info{};
-  if (nrhs == 0) return H2_OK;
+  if (nrhs == 0) return;
   if (!b || !z) throw Error(H2_EINVAL, "b and z must not be NULL");
   if (ldb < H.S.n || ldz < H.S.n) throw Error(H2_EINVAL, "leading dimension smaller than n");
-  const auto t0 = std::chrono::steady_clock::now();
+}
+
+// Device bytes of a solve: the solver's workspace plus the two n x nrhs product buffers
+size_t solve_bytes(const h2_handle_s& H, int nrhs, int dtype, const h2_solve_params& p, size_t* vec) {
   const KLayout L = klayout(dtype, H.S.n, nrhs, p);
-  const size_t es = cx ? 16 : 8;
-  const size_t vec = align256(static_cast<size_t>(H.S.n) * nrhs * es);
-  // the handle keeps the solver's workspace between calls; it grows when a call needs more
-  const size_t need = L.bytes + 2 * vec;
-  if (H.kws.bytes < need) {
-    H2_HIP(hipStreamSynchronize(st));
-    H.kws.alloc(need);
-  }
-  if (H.kstat_n < 3 * nrhs) {
-    if (H.kstat) (void)hipHostFree(H.kstat);
-    H.kstat = nullptr;
-    H.kstat_n = 0;
-    H2_HIP(hipHostMalloc(reinterpret_cast<void**>(&H.kstat), 3 * static_cast<size_t>(nrhs) * 8,
-                         hipHostMallocDefault));
-    H.kstat_n = 3 * nrhs;
-  }
-  char* base = H.kws.as<char>();
-  void* X = base + L.bytes;
-  void* Y = base + L.bytes + vec;
-  KSolver K(dtype, H.S.n, nrhs, p, base, L.bytes, H.kstat);
+  *vec = align256(static_cast<size_t>(H.S.n) * nrhs * (dtype == H2_C128 ? 16 : 8));
+  return L.bytes + 2 * *vec;
+}
+
+// The solve loop on a given workspace: one product per step, then the solver's decision.
+int run_solve(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+              const h2_solve_params& p, h2_solve_info& info, hipStream_t st, char* ws, double* host_status,
+              bool may_alloc) {
+  const auto t0 = std::chrono::steady_clock::now();
+  size_t vec = 0;
+  const size_t need = solve_bytes(H, nrhs, dtype, p, &vec);
+  const size_t kbytes = need - 2 * vec;
+  void* X = ws + kbytes;
+  void* Y = ws + kbytes + vec;
+  KSolver K(dtype, H.S.n, nrhs, p, ws, kbytes, host_status);
   K.begin(b, ldb, z, ldz, st);
   int state = H2_KS_PRODUCT;
   while (true) {
     int flags = 0;
     state = K.next(X, H.S.n, &flags, st);
     if (state != H2_KS_PRODUCT) break;
-    matvec(H, nrhs, dtype, X, H.S.n, Y, H.S.n, 1.0, flags | H2_OVERWRITE, st);
+    matvec(H, nrhs, dtype, X, H.S.n, Y, H.S.n, 1.0, flags | H2_OVERWRITE, st, may_alloc);
     K.advance(Y, H.S.n, st);
     H2_HIP(hipStreamSynchronize(st));
     state = K.poll();
@@ -930,6 +941,76 @@ int solve_multi(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb,
   info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (state == H2_KS_FAILED) throw Error(H2_ENOTCONV, K.message);
   return state == H2_KS_DONE ? H2_OK : H2_ENOTCONV;
+}
+}  // namespace
+
+int solve_multi(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+                const h2_solve_params& p, h2_solve_info& info, hipStream_t st) {
+  check_solve_args(H, nrhs, dtype, b, ldb, z, ldz, p);
+  info = h2_solve_info{};
+  if (nrhs == 0) return H2_OK;
+  size_t vec = 0;
+  // the handle keeps the solver's workspace between calls; it grows when a call needs more
+  const size_t need = solve_bytes(H, nrhs, dtype, p, &vec);
+  if (H.kws.bytes < need) {
+    H2_HIP(hipStreamSynchronize(st));
+    H.kws.alloc(need);
+  }
+  if (H.kstat_n < 3 * nrhs) {
+    if (H.kstat) (void)hipHostFree(H.kstat);
+    H.kstat = nullptr;
+    H.kstat_n = 0;
+    H2_HIP(hipHostMalloc(reinterpret_cast<void**>(&H.kstat), 3 * static_cast<size_t>(nrhs) * 8,
+                         hipHostMallocDefault));
+    H.kstat_n = 3 * nrhs;
+  }
+  return run_solve(H, nrhs, dtype, b, ldb, z, ldz, p, info, st, H.kws.as<char>(), H.kstat, true);
+}
+
+// ============================================================================ allocation-free h2_solve
+// The solver's workspace and the product buffers live in one file-scope device
+// array: each GPU holds its own copy from the time the library's code object is
+// loaded on it until the process ends.  In host code `scratch` only names the
+// symbol; its device address on the current GPU comes from hipGetSymbolAddress,
+// looked up once per device and kept.
+namespace {
+constexpr size_t kScratchBytes = static_cast<size_t>(H2_NOALLOC_SCRATCH_BYTES);
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+char* scratch_on_current_device() {
+  int dev = 0;
+  H2_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(H2_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    H2_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error(H2_EHIP, "no device address for the solver scratch");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
+}  // namespace
+
+int solve_noalloc(h2_handle_s& H, int nrhs, int dtype, const void* b, int64_t ldb, void* z, int64_t ldz,
+                  const h2_solve_params& p, h2_solve_info& info, hipStream_t st) {
+  check_solve_args(H, nrhs, dtype, b, ldb, z, ldz, p);
+  info = h2_solve_info{};
+  if (nrhs == 0) return H2_OK;
+  if (nrhs > H2_NOALLOC_MAX_RHS)
+    throw Error(H2_EINVAL, "h2_solve_noalloc takes at most " + std::to_string(H2_NOALLOC_MAX_RHS) +
+                               " right-hand sides");
+  size_t vec = 0;
+  const size_t need = solve_bytes(H, nrhs, dtype, p, &vec);
+  if (need > kScratchBytes)
+    throw Error(H2_EINVAL, "the solve needs " + std::to_string(need) + " bytes of scratch; h2_solve_noalloc has " +
+                               std::to_string(kScratchBytes));
+  char* ws = scratch_on_current_device();
+  double status[3 * H2_NOALLOC_MAX_RHS];  // pageable: read after the stream is synchronised
+  return run_solve(H, nrhs, dtype, b, ldb, z, ldz, p, info, st, ws, status, false);
 }
 
 }  // namespace h2

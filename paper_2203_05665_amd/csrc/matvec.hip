@@ -1365,7 +1365,7 @@ void matvec_cx(h2_handle_s& H, int dtype, const void* x, void* y, double alpha, 
 }  // namespace
 
 void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy, double alpha,
-            int flags, hipStream_t st) {
+            int flags, hipStream_t st, bool may_alloc) {
   if (H.host_only) throw Error(H2_EINVAL, "handle was built with H2_HOST_ONLY");
   if (nrhs < 0) throw Error(H2_EINVAL, "nrhs must be >= 0");
   const bool cx = dtype == H2_C128 || dtype == H2_C64;
@@ -1377,8 +1377,10 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
   if (ldx < H.S.n || ldy < H.S.n) throw Error(H2_EINVAL, "leading dimension smaller than n");
   const bool acc64 = (flags & H2_ACC_F64) != 0;
   H.overwrite = (flags & H2_OVERWRITE) != 0;
+  const bool multi = nrhs >= 2 && !acc64 && matvec_multi_supported(H) &&
+                     (may_alloc || matvec_multi_ready(H, nrhs, dtype));
   if (cx) {
-    if (nrhs >= 2 && !acc64 && matvec_multi_supported(H)) {
+    if (multi) {
       matvec_multi(H, nrhs, dtype, x, ldx, y, ldy, alpha, st);
       return;
     }
@@ -1393,7 +1395,7 @@ void matvec(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, voi
     return;
   }
   const size_t es = dtype == H2_R64 ? 8 : 4;
-  if (nrhs >= 2 && !acc64 && matvec_multi_supported(H)) {
+  if (multi) {
     matvec_multi(H, nrhs, dtype, x, ldx, y, ldy, alpha, st);
     return;
   }

@@ -1176,10 +1176,22 @@ bool matvec_multi_supported(const h2_handle_s& H) {
   return true;
 }
 
+// columns per pass of the many-RHS path and the workspace bytes it needs
+static int pass_columns(const h2_handle_s& H, int nrhs, int dtype) {
+  const bool cx = dtype == H2_C128 || dtype == H2_C64;
+  return cx ? 32 : H.tune_pass == 32 || H.tune_pass == 64 ? H.tune_pass : (nrhs <= 32 ? 32 : 64);
+}
+
+bool matvec_multi_ready(const h2_handle_s& H, int nrhs, int dtype) {
+  const int rp = pass_columns(H, nrhs, dtype);
+  const size_t need_v = static_cast<size_t>(H.S.n) * rp * 4, need_h = static_cast<size_t>(H.S.nclusters) * 64 * rp * 4;
+  return H.mxc.bytes >= need_v && H.mxhat.bytes >= need_h && H.morder.p != nullptr;
+}
+
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
                   double alpha, hipStream_t st) {
   const bool cx = dtype == H2_C128 || dtype == H2_C64;
-  const int rp = cx ? 32 : H.tune_pass == 32 || H.tune_pass == 64 ? H.tune_pass : (nrhs <= 32 ? 32 : 64);
+  const int rp = pass_columns(H, nrhs, dtype);
   const Structure& S = H.S;
   const size_t need_v = static_cast<size_t>(S.n) * rp * 4, need_h = static_cast<size_t>(S.nclusters) * 64 * rp * 4;
   if (H.mxc.bytes < need_v || H.mxhat.bytes < need_h) {

@@ -96,6 +96,8 @@ def lib():
                                 C.c_double, C.c_int, C.c_void_p]
         L.h2_solve.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                C.POINTER(h2_solve_params), C.POINTER(h2_solve_info), C.c_void_p]
+        L.h2_solve_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                       C.POINTER(h2_solve_params), C.POINTER(h2_solve_info), C.c_void_p]
         L.h2_krylov_workspace.argtypes = [C.c_int, C.c_int64, C.c_int, C.POINTER(h2_solve_params)]
         L.h2_krylov_workspace.restype = C.c_int64
         L.h2_krylov_create.argtypes = [C.c_int, C.c_int64, C.c_int, C.POINTER(h2_solve_params), C.c_void_p,
@@ -123,7 +125,7 @@ def lib():
         L.h2_recompress.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(h2_recompress_info), C.c_void_p]
         L.h2_tune.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(h2_tune_info), C.c_void_p]
         L.h2_set_tuning.argtypes = [C.c_void_p, C.c_int, C.c_int]
-        for f in ("build_h2", "h2_matvec", "h2_solve", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
+        for f in ("build_h2", "h2_matvec", "h2_solve", "h2_solve_noalloc", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
                   "h2_krylov_dots", "h2_krylov_update", "h2_recompress", "h2_tune", "h2_set_tuning",
                   "h2_krylov_create", "h2_krylov_begin", "h2_krylov_next", "h2_krylov_advance", "h2_krylov_poll",
                   "h2_krylov_residuals", "h2_krylov_solution", "h2_stream_read"):
@@ -223,10 +225,10 @@ def solve_params(method="cg", rtol=1e-8, maxit=1000, restart=50, refine=False, i
 
 
 def h2_solve(h, b, z, method="cg", rtol=1e-8, maxit=1000, restart=50, refine=False, inner_rtol=1e-4,
-             stream=None, check=True):
+             stream=None, check=True, noalloc=False):
     """Solves G~ Z = B for float64 (complex128 for Helmholtz) device blocks b, z of
     shape (n,) or (n, nrhs) with contiguous columns; z holds the initial guess
-    and the result."""
+    and the result.  noalloc: the allocation-free entry point h2_solve_noalloc."""
     import torch
     want = torch.complex128 if b.is_complex() else torch.float64
     if b.dtype != want or z.dtype != want:
@@ -241,7 +243,8 @@ def h2_solve(h, b, z, method="cg", rtol=1e-8, maxit=1000, restart=50, refine=Fal
     p = solve_params(method, rtol, maxit, restart, refine, inner_rtol)
     info = h2_solve_info()
     dt = H2_C128 if b.is_complex() else H2_R64
-    rc = lib().h2_solve(h, rb, dt, pb, ldb, pz, ldz, C.byref(p), C.byref(info), _stream(stream))
+    fn = lib().h2_solve_noalloc if noalloc else lib().h2_solve
+    rc = fn(h, rb, dt, pb, ldb, pz, ldz, C.byref(p), C.byref(info), _stream(stream))
     if rc != H2_ENOTCONV or check:
         _check(rc)
     return dict(iterations=info.iterations, outer=info.outer, rel_residual=info.rel_residual,
