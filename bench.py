@@ -216,24 +216,30 @@ def host_cores():
 def read_ceiling(torch, h2, gib=4.0, reps=10):
     """HBM read rate of the library's read-only streaming kernel (16-byte
     non-temporal loads, as the product kernels issue them) over `gib` GiB, far
-    beyond the caches; HIP events on the launch stream, mean over `reps`."""
+    beyond the caches, with 4, 8 and 16 loads in flight per thread; HIP events on
+    the launch stream, mean over `reps`; the best of the three is the ceiling."""
     nbytes = int(gib * (1 << 30))
     buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    sink = torch.zeros(8192, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(4096, dtype=torch.int32, device="cuda")
     s = torch.cuda.current_stream()
-    for _ in range(2):
-        h2.h2_stream_read(buf, sink, stream=s.cuda_stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        h2.h2_stream_read(buf, sink, stream=s.cuda_stream)
-    e1.record(s)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    rates = {}
+    for loads in (4, 8, 16):
+        for _ in range(2):
+            h2.h2_stream_read(buf, sink, loads, stream=s.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            h2.h2_stream_read(buf, sink, loads, stream=s.cuda_stream)
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rates[loads] = {"avg_launch_ms": ms, "GBs": nbytes / (ms * 1e-3) / 1e9}
     del buf, sink
     torch.cuda.empty_cache()
-    return {"kernel": "stream_read", "bytes_per_launch": nbytes, "avg_launch_ms": ms,
-            "GBs": nbytes / (ms * 1e-3) / 1e9}
+    best = max(rates, key=lambda k: rates[k]["GBs"])
+    return {"kernel": "stream_read", "bytes_per_launch": nbytes, "loads_in_flight": best,
+            "avg_launch_ms": rates[best]["avg_launch_ms"], "GBs": rates[best]["GBs"],
+            "by_loads_in_flight": rates}
 
 
 def copy_probe(torch, gib=2.0, reps=5):
@@ -385,7 +391,8 @@ def run_multi(args, workload, full=True):
     X = X.t().contiguous().t()
     Y = torch.zeros_like(X)
     tuning = A.tune(R, "f64", reps=5)  # tile shapes for R columns, before the timed region
-    log("bench: tuning %s" % tuning)
+    tuning_order = A.tune(R, "f64", reps=5, knob="row_order")
+    log("bench: tuning %s %s" % (tuning, tuning_order))
     el, prof = measure(A, X, Y, args.steps, args.warmup, torch, h2)
     try:
         graph = graph_timing(A, X, Y, torch)  # the whole pass captured once, replayed
@@ -412,7 +419,7 @@ def run_multi(args, workload, full=True):
         "path": {"flops": flops_total, "TFLOPs": flops_total / (el / args.steps) / 1e12,
                  "phase_ms": {kk: v[0] / max(1, v[1]) for kk, v in prof.items()}, "build_s": build_s,
                  "device_bytes": info["bytes_total"]},
-        "tuning": tuning, "graph_replay": graph,
+        "tuning": tuning, "tuning_row_order": tuning_order, "graph_replay": graph,
     }
     A.close()
     del A
@@ -751,7 +758,7 @@ def main():
         log("bench: many right-hand sides (cube786k, 64 columns)")
         mr = run_multi(args, "cube786k_m4_r64", full=False)
         out["multi_rhs"] = {k: mr[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "roofline", "path",
-                                               "tuning", "graph_replay")}
+                                               "tuning", "tuning_row_order", "graph_replay")}
     if headline and not args.no_serve:
         log("bench: serving leg (%d requests at %.1f/s)" % (args.bench_serve_requests, args.bench_serve_rate))
         out["serving"] = run_serve(args, args.bench_serve_requests, args.bench_serve_rate, args.bench_serve_deadline_s)

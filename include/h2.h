@@ -309,6 +309,15 @@ int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* inf
  *                         bases): lanes per block-row slot of a wave, 16 (four
  *                         blocks of a row cluster at a time, needs k <= 16) or 32
  *                         (two).  Built-in rule: 16 if k <= 16, else 32.
+ *   H2_TUNE_ROW_ORDER     many right-hand sides on the matrix-core path (real
+ *                         or complex): the order in which the workgroups of the
+ *                         coupling kernels take the row clusters, 1 (eight
+ *                         contiguous ranges of equal work, one per XCD: rows
+ *                         that share column clusters share an L2) or 2 (natural
+ *                         order, four rows per workgroup, workgroups dealt
+ *                         round-robin to the XCDs: neighbouring rows run at the
+ *                         same time on every XCD).  Built-in rule: 1.  Only
+ *                         h2_tune_knob tunes it.
  * h2_tune runs the product the way h2_matvec(h, nrhs, dtype, ...) would, with
  * every value of the knob that path has: one untimed and `reps` timed products
  * each on library-owned vectors (allocated for the call), timed with HIP events
@@ -330,6 +339,7 @@ int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* inf
 #define H2_TUNE_NONE (-1)
 #define H2_TUNE_PASS_COLUMNS 0
 #define H2_TUNE_SMALL_SLOT 1
+#define H2_TUNE_ROW_ORDER 2
 typedef struct {
   int knob;
   int ncand;
@@ -338,6 +348,9 @@ typedef struct {
   int chosen;
 } h2_tune_info;
 int h2_tune(h2_handle h, int nrhs, int dtype, int reps, h2_tune_info* info, void* stream);
+/* h2_tune for one given knob of the path (info.knob = H2_TUNE_NONE if the path
+ * does not have it). */
+int h2_tune_knob(h2_handle h, int knob, int nrhs, int dtype, int reps, h2_tune_info* info, void* stream);
 int h2_set_tuning(h2_handle h, int knob, int value);
 
 int h2_info(h2_handle h, h2_stats* out);
@@ -387,13 +400,14 @@ int h2_krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, in
                      void* stream);
 
 /* Measurement utility: reads `bytes` (a positive multiple of 16) of DEVICE memory
- * at `data` (16-byte aligned) with 16-byte non-temporal loads, four in flight per
- * thread, the way the bandwidth-bound product kernels stream their data, and
- * writes nothing in practice (`sink`, DEVICE memory of at least
- * 4 * min(8192, ceil(bytes / 16384)) bytes, keeps the loads live).  Timed by the
- * caller; bytes / time is the HBM read rate a plain kernel reaches, the measured
- * ceiling beside the vendor peak.  Asynchronous on `stream`. */
-int h2_stream_read(const void* data, int64_t bytes, void* sink, int64_t sink_bytes, void* stream);
+ * at `data` (16-byte aligned) with 16-byte non-temporal loads, `loads` (4, 8 or
+ * 16) in flight per thread, each workgroup on contiguous tiles of 256 x loads
+ * vectors, the way the bandwidth-bound product kernels stream their data, and
+ * writes nothing in practice (`sink`, DEVICE memory of at least 16 KiB, keeps
+ * the loads live).  Timed by the caller; bytes / time is the HBM read rate a
+ * plain kernel reaches, the measured ceiling beside the vendor peak.
+ * Asynchronous on `stream`. */
+int h2_stream_read(const void* data, int64_t bytes, int loads, void* sink, int64_t sink_bytes, void* stream);
 
 /* Per-phase device timing of h2_matvec (HIP events on the call's stream).
  * h2_profile(h, 1) enables and clears; h2_profile(h, 0) disables.

@@ -142,6 +142,27 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
         H->near_ptr.upload(S.near_ptr);
         H->near_col.upload(S.near_col);
         H->panel_off.upload(S.panel_off);
+        {
+          std::vector<h2::NearRow> rows(S.leaves.size());
+          std::vector<h2::NearBlock> blks(S.near_col.size());
+          bool fits = true;
+          for (size_t l = 0; l < S.leaves.size(); ++l) {
+            const int32_t tau = S.leaves[l];
+            const int64_t nb = S.near_ptr[l + 1] - S.near_ptr[l];
+            rows[l] = {S.panel_off[l], S.near_ptr[l], S.cbegin[tau], S.cend[tau] - S.cbegin[tau],
+                       static_cast<int32_t>(nb), tau};
+            int32_t c = 0;
+            for (int64_t b = S.near_ptr[l]; b < S.near_ptr[l + 1]; ++b) {
+              const int32_t s = S.near_col[b], w = S.cend[s] - S.cbegin[s];
+              blks[b] = {S.cbegin[s], w, c, 0};
+              c += w;
+            }
+            fits = fits && rows[l].r <= 64 && nb <= 256;
+          }
+          H->near_rows.upload(rows);
+          H->near_blocks.upload(blks);
+          H->near64 = fits;
+        }
         std::vector<int32_t> ul;
         H->up_ptr.assign(S.depth + 1, 0);
         for (int l = 0; l < S.depth; ++l) {
@@ -150,6 +171,19 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
           H->up_ptr[l + 1] = static_cast<int64_t>(ul.size());
         }
         H->up_list.upload(ul);
+        // levels with few clusters from the root down: their transfers run in one workgroup
+        auto top_levels = [&](int64_t most, bool up) {
+          int t = 0;
+          while (t < S.depth && (up ? H->up_ptr[t + 1] - H->up_ptr[t] : S.level_ptr[t + 2] - S.level_ptr[t + 1]) <= most)
+            ++t;
+          return t;
+        };
+        H->up_top = top_levels(64, true);
+        H->down_top = top_levels(64, false);
+        H->mup_top = top_levels(8, true);
+        H->mdown_top = top_levels(8, false);
+        H->up_ptr_dev.upload(H->up_ptr);
+        H->level_ptr_dev.upload(S.level_ptr);
         if (S.sym_s) {
           H->adm_in_ptr.upload(S.adm_in_ptr);
           H->adm_in_blk.upload(S.adm_in_blk);
@@ -313,6 +347,15 @@ int h2_tune(h2_handle h, int nrhs, int dtype, int reps, h2_tune_info* info, void
     if (!h) return fail(H2_EINVAL, "NULL handle");
     h2_tune_info tmp{};
     h2::tune(*h, nrhs, dtype, reps, info ? *info : tmp, static_cast<hipStream_t>(stream));
+    return H2_OK;
+  });
+}
+
+int h2_tune_knob(h2_handle h, int knob, int nrhs, int dtype, int reps, h2_tune_info* info, void* stream) {
+  return guarded([&]() -> int {
+    if (!h) return fail(H2_EINVAL, "NULL handle");
+    h2_tune_info tmp{};
+    h2::tune(*h, nrhs, dtype, reps, info ? *info : tmp, static_cast<hipStream_t>(stream), knob);
     return H2_OK;
   });
 }
@@ -495,9 +538,9 @@ int h2_krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, in
   });
 }
 
-int h2_stream_read(const void* data, int64_t bytes, void* sink, int64_t sink_bytes, void* stream) {
+int h2_stream_read(const void* data, int64_t bytes, int loads, void* sink, int64_t sink_bytes, void* stream) {
   return guarded([&]() -> int {
-    h2::stream_read_launch(data, bytes, sink, sink_bytes, static_cast<hipStream_t>(stream));
+    h2::stream_read_launch(data, bytes, loads, sink, sink_bytes, static_cast<hipStream_t>(stream));
     return H2_OK;
   });
 }

@@ -53,6 +53,21 @@ struct DBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// One row leaf of the near field for near_backward64: its panel, its first near
+// block, its triangles and its cluster.
+struct NearRow {
+  int64_t panel_off;  // element offset of the panel
+  int64_t bfirst;     // first near block (index into near_col)
+  int32_t b0, r;      // first triangle (cluster order) and triangle count
+  int32_t nb, tau;    // near blocks of the row; cluster id
+};
+
+// One near block for near_backward64: first triangle s0 and width w of the column
+// leaf sigma, first column cb of the block in the row's panel (pad: unused).
+struct NearBlock {
+  int32_t s0, w, cb, pad;
+};
+
 // bf16 storage element (upper half of an IEEE float).
 struct bf16 {
   uint16_t v;
@@ -72,10 +87,22 @@ struct h2_handle_s {
   // device structure
   h2::DBuf perm, cbegin, cend, parent, child0, child1, leaves, adm_ptr, adm_col, near_ptr, near_col,
       panel_off, up_list, pts;
+  // near_backward64's descriptors (h2::NearRow per leaf, h2::NearBlock per near
+  // block); near64: every leaf holds at most 64 triangles and every row at most 256
+  // near blocks, so that kernel applies
+  h2::DBuf near_rows, near_blocks;
+  bool near64 = false;
   // on-the-fly coupling: cluster centres (FP64, 3 per cluster) and point offsets from
   // the centre (3 x m per cluster, FP32 and FP64)
   h2::DBuf ctr, off32, off64;
   std::vector<int64_t> up_ptr;  // host offsets into up_list per level
+  // the top levels of the transfer sweeps that run in one workgroup: up levels
+  // 0..up_top-1, down parent levels 0..down_top-1 (each at most 64 clusters, four
+  // rounds of the single-vector kernel's 16 waves); mup_top / mdown_top likewise for
+  // the many-column sweeps, whose per-cluster work is larger (at most 8 clusters a
+  // level, one round of that kernel's 8 waves)
+  int up_top = 0, down_top = 0, mup_top = 0, mdown_top = 0;
+  h2::DBuf up_ptr_dev, level_ptr_dev;
   // matrix data
   h2::DBuf Vf, Vb, F, ET, Smat, Nmat;
   // H2_F32_SBF16: the coupling matrices also in FP32, for products with FP64
@@ -97,6 +124,8 @@ struct h2_handle_s {
   // tile choices (0: the built-in rule), set by h2_tune or h2_set_tuning
   int tune_pass = 0;  // right-hand sides per many-RHS pass: 32 or 64
   int tune_slot = 0;  // lanes per block-row slot of the small-k coupling: 16 or 32
+  int tune_order = 0; // row order of the many-RHS coupling: 1 XCD chunks, 2 interleaved (0: rule, 1)
+  int morder_kind = 0;  // the order morder holds
   bool overwrite = false;  // the current product assigns y <- alpha G~ x (H2_OVERWRITE)
   // h2_solve: the Krylov solver's workspace and its pinned status (kept between
   // calls, grown when a call needs more)
@@ -131,9 +160,10 @@ void krylov_dots(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_
 void krylov_update(int dtype, int nrhs, int nvec, int64_t n, const void* Q, int64_t qr, int64_t qv, const void* h,
                    double sign, void* W, int64_t wr, hipStream_t st);
 void recompress(h2_handle_s& H, double eps, int max_rank, h2_recompress_info& info, hipStream_t st);
-void tune(h2_handle_s& H, int nrhs, int dtype, int reps, h2_tune_info& info, hipStream_t st);
+void tune(h2_handle_s& H, int nrhs, int dtype, int reps, h2_tune_info& info, hipStream_t st, int knob = -2);
+void ensure_row_order(h2_handle_s& H);
 void set_tuning(h2_handle_s& H, int knob, int value);
-void stream_read_launch(const void* data, int64_t bytes, void* sink, int64_t sink_bytes, hipStream_t st);
+void stream_read_launch(const void* data, int64_t bytes, int loads, void* sink, int64_t sink_bytes, hipStream_t st);
 hipEvent_t prof_event(h2_handle_s& H);
 void prof_record(h2_handle_s& H, int phase, hipEvent_t a, hipEvent_t b);
 }  // namespace h2

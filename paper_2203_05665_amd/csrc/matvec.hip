@@ -115,18 +115,20 @@ __device__ inline double bcast(double v, int j) {
   return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
 }
 
-// acc += sum_{j < cnt} A[j * stride] * (value of xv in lane j), 8 loads in flight
-template <typename ST, typename AT>
+// acc += sum_{j < cnt} A[j * stride] * (value of xv in lane j) for cnt <= 64, with
+// xv zero in lanes cnt..63.  G loads in flight (G divides 64); the last group
+// re-reads column cnt - 1 in place of the columns past cnt, whose x is zero, so
+// every group issues all of its loads before the first multiply
+template <typename ST, typename AT, int G = 8>
 __device__ inline AT stream_dot(const ST* __restrict__ A, int64_t stride, int cnt, AT xv, AT acc) {
-  int j = 0;
-  for (; j + 8 <= cnt; j += 8) {
-    AT a[8];
+  static_assert(64 % G == 0, "groups tile the 64 lanes");
+  for (int j = 0; j < cnt; j += G) {
+    AT a[G];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = ld<ST, AT>(A + (j + u) * stride);
+    for (int u = 0; u < G; ++u) a[u] = ld<ST, AT>(A + min(j + u, cnt - 1) * stride);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += a[u] * bcast(xv, j + u);
+    for (int u = 0; u < G; ++u) acc += a[u] * bcast(xv, j + u);
   }
-  for (; j < cnt; ++j) acc += ld<ST, AT>(A + j * stride) * bcast(xv, j);
   return acc;
 }
 
@@ -157,16 +159,12 @@ __global__ __launch_bounds__(256) void leaf_forward(int nleaves, int k, const in
 }
 
 // ---------------------------------------------------------------- transfers
-// up: one wave per non-leaf cluster of a level; lane = parent index nu
+// One wave per cluster.  Dense transfers (any k): lane = parent index nu (up) or
+// child index nu' (down), the matrix read as coalesced rows (F and its transpose
+// ET are both stored).
 template <typename ST, typename AT>
-__global__ __launch_bounds__(256) void transfer_up(int count, int k, const int32_t* __restrict__ list,
-                                                   const int32_t* __restrict__ child0,
-                                                   const int32_t* __restrict__ child1, const ST* __restrict__ F,
-                                                   AT* __restrict__ xhat) {
-  const int w = blockIdx.x * 4 + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (w >= count) return;
-  const int32_t c = list[w];
+__device__ inline void up_dense(int32_t c, int k, int lane, const int32_t* __restrict__ child0,
+                                const int32_t* __restrict__ child1, const ST* __restrict__ F, AT* __restrict__ xhat) {
   const int32_t ch[2] = {child0[c], child1[c]};
   const int64_t kk = static_cast<int64_t>(k) * k;
   for (int nu0 = 0; nu0 < k; nu0 += 64) {
@@ -184,14 +182,9 @@ __global__ __launch_bounds__(256) void transfer_up(int count, int k, const int32
   }
 }
 
-// down: one wave per cluster of a level (all have parents); lane = child index nu'
 template <typename ST, typename AT>
-__global__ __launch_bounds__(256) void transfer_down(int first, int count, int k, const int32_t* __restrict__ parent,
-                                                     const ST* __restrict__ ET, AT* __restrict__ yhat) {
-  const int w = blockIdx.x * 4 + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (w >= count) return;
-  const int32_t c = first + w;
+__device__ inline void down_dense(int32_t c, int k, int lane, const int32_t* __restrict__ parent,
+                                  const ST* __restrict__ ET, AT* __restrict__ yhat) {
   const int64_t kk = static_cast<int64_t>(k) * k;
   const AT* yp = yhat + static_cast<int64_t>(parent[c]) * k;
   for (int n0 = 0; n0 < k; n0 += 64) {
@@ -227,14 +220,8 @@ __device__ inline AT kron_axis(AT t, const ST* __restrict__ e, int lane, int shi
 
 // up: x^_c = sum over the two children a of E_a^T x^_a (Algorithm 1)
 template <typename ST, typename AT>
-__global__ __launch_bounds__(256) void transfer_up_kron(int count, const int32_t* __restrict__ list,
-                                                        const int32_t* __restrict__ child0,
-                                                        const int32_t* __restrict__ child1,
-                                                        const ST* __restrict__ E1, AT* __restrict__ xhat) {
-  const int w = blockIdx.x * 4 + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (w >= count) return;
-  const int32_t c = list[w];
+__device__ inline void up_kron(int32_t c, int lane, const int32_t* __restrict__ child0,
+                               const int32_t* __restrict__ child1, const ST* __restrict__ E1, AT* __restrict__ xhat) {
   const int32_t ch[2] = {child0[c], child1[c]};
   AT acc = 0;
 #pragma unroll
@@ -251,18 +238,72 @@ __global__ __launch_bounds__(256) void transfer_up_kron(int count, const int32_t
 
 // down: y^_c += E_c y^_parent(c) (Algorithm 2)
 template <typename ST, typename AT>
-__global__ __launch_bounds__(256) void transfer_down_kron(int first, int count, const int32_t* __restrict__ parent,
-                                                          const ST* __restrict__ E1, AT* __restrict__ yhat) {
-  const int w = blockIdx.x * 4 + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (w >= count) return;
-  const int64_t c = first + w;
-  const ST* e = E1 + c * 48;
+__device__ inline void down_kron(int32_t c, int lane, const int32_t* __restrict__ parent, const ST* __restrict__ E1,
+                                 AT* __restrict__ yhat) {
+  const ST* e = E1 + static_cast<int64_t>(c) * 48;
   AT t = yhat[static_cast<int64_t>(parent[c]) * 64 + lane];
   t = kron_axis<ST, AT>(t, e, lane, 0, false);
   t = kron_axis<ST, AT>(t, e + 16, lane, 2, false);
   t = kron_axis<ST, AT>(t, e + 32, lane, 4, false);
-  yhat[c * 64 + lane] += t;
+  yhat[static_cast<int64_t>(c) * 64 + lane] += t;
+}
+
+// one level: one wave per cluster (E: E1 for the Kronecker form, else F / ET)
+template <typename ST, typename AT, bool KRON>
+__global__ __launch_bounds__(256) void transfer_up(int count, int k, const int32_t* __restrict__ list,
+                                                   const int32_t* __restrict__ child0,
+                                                   const int32_t* __restrict__ child1, const ST* __restrict__ E,
+                                                   AT* __restrict__ xhat) {
+  const int w = blockIdx.x * 4 + threadIdx.x / 64;
+  if (w >= count) return;
+  if (KRON) up_kron<ST, AT>(list[w], threadIdx.x % 64, child0, child1, E, xhat);
+  else up_dense<ST, AT>(list[w], k, threadIdx.x % 64, child0, child1, E, xhat);
+}
+
+template <typename ST, typename AT, bool KRON>
+__global__ __launch_bounds__(256) void transfer_down(int first, int count, int k, const int32_t* __restrict__ parent,
+                                                     const ST* __restrict__ E, AT* __restrict__ yhat) {
+  const int w = blockIdx.x * 4 + threadIdx.x / 64;
+  if (w >= count) return;
+  if (KRON) down_kron<ST, AT>(first + w, threadIdx.x % 64, parent, E, yhat);
+  else down_dense<ST, AT>(first + w, k, threadIdx.x % 64, parent, E, yhat);
+}
+
+// The top levels, which hold few clusters each, in one workgroup of 16 waves:
+// level by level (deepest first going up, root first going down), a workgroup
+// barrier between levels (a level reads what the previous one wrote), so their
+// dependent launches become one.  lev: the levels' offsets into list (up), or the
+// cluster offsets of the levels (down).
+constexpr int kTopWaves = 16;
+
+template <typename ST, typename AT, bool KRON>
+__global__ __launch_bounds__(64 * kTopWaves) void transfer_up_top(int nlev, const int64_t* __restrict__ lev, int k,
+                                                                  const int32_t* __restrict__ list,
+                                                                  const int32_t* __restrict__ child0,
+                                                                  const int32_t* __restrict__ child1,
+                                                                  const ST* __restrict__ E, AT* __restrict__ xhat) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int l = nlev - 1; l >= 0; --l) {
+    for (int64_t w = lev[l] + wave; w < lev[l + 1]; w += kTopWaves) {
+      if (KRON) up_kron<ST, AT>(list[w], lane, child0, child1, E, xhat);
+      else up_dense<ST, AT>(list[w], k, lane, child0, child1, E, xhat);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename ST, typename AT, bool KRON>
+__global__ __launch_bounds__(64 * kTopWaves) void transfer_down_top(int nlev, const int32_t* __restrict__ level_ptr,
+                                                                    int k, const int32_t* __restrict__ parent,
+                                                                    const ST* __restrict__ E, AT* __restrict__ yhat) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int l = 0; l < nlev; ++l) {
+    for (int32_t c = level_ptr[l + 1] + wave; c < level_ptr[l + 2]; c += kTopWaves) {
+      if (KRON) down_kron<ST, AT>(c, lane, parent, E, yhat);
+      else down_dense<ST, AT>(c, k, lane, parent, E, yhat);
+    }
+    __syncthreads();
+  }
 }
 
 // the transfer phases of one product: Kronecker form for k = 64, dense otherwise
@@ -711,7 +752,7 @@ void launch_otf(h2_handle_s& H, const AT* xh, AT* yh, hipStream_t st) {
 // one 256-thread workgroup per row leaf tau; lane = row of tau.  The near blocks
 // of the row are dealt round-robin to the four waves; a wave stages x|sigma one
 // value per lane and streams the block's columns (each column is |tau|
-// contiguous entries of the column-major panel) with 8 loads in flight.  The
+// contiguous entries of the column-major panel) with 16 loads in flight.  The
 // columns of V_tau (multiplied by y^_tau) are split between the waves the same
 // way.  LDS sums the four partial results in a fixed order.
 template <typename ST, typename AT>
@@ -747,7 +788,7 @@ __global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const i
       if (((bb - bfirst) & 3) == wave) {
         for (int j0 = 0; j0 < w; j0 += 64) {
           const AT xv = j0 + lane < w ? xc[s0 + j0 + lane] : AT(0);
-          acc = stream_dot<ST, AT>(P + (colbase + j0) * r + is, r, min(64, w - j0), xv, acc);
+          acc = stream_dot<ST, AT, 16>(P + (colbase + j0) * r + is, r, min(64, w - j0), xv, acc);
         }
       }
       colbase += w;
@@ -757,13 +798,132 @@ __global__ __launch_bounds__(256) void near_backward(int nleaves, int k, const i
     const int n0 = wave * kq, n1 = min(k, n0 + kq);
     for (int q0 = n0; q0 < n1; q0 += 64) {
       const AT yv = q0 + lane < n1 ? yh[q0 + lane] : AT(0);
-      acc = stream_dot<ST, AT>(Vl + static_cast<int64_t>(q0) * r + is, r, min(64, n1 - q0), yv, acc);
+      acc = stream_dot<ST, AT, 16>(Vl + static_cast<int64_t>(q0) * r + is, r, min(64, n1 - q0), yv, acc);
     }
     part[wave][lane] = acc;
     __syncthreads();
     if (wave == 0 && i < r) yc[b0 + i] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     __syncthreads();
   }
+}
+
+// Leaves of at most 64 triangles and at most 256 near blocks per row: the same
+// product with the column stream kept busy from the first column to the last.
+// The blocks of the row go round-robin to the four waves as above; a wave holds its
+// blocks' descriptors (first triangle s0 and width w of sigma, first panel column
+// cb) one per lane and walks its columns in groups of G.  The G loads of the next
+// group, which may open the next block, are issued before the current group is
+// multiplied, so G to 2G loads of |tau| entries stay in flight.  A group that runs
+// past its block's last column re-reads that column, whose x weight there is
+// zero.  The leaf-backward operands (this wave's columns of V_tau and of y^_tau)
+// are loaded first, so their latency overlaps the start of the stream, and each
+// row's and block's descriptors are one load each.
+template <typename ST, typename AT, int G>
+__global__ __launch_bounds__(256) void near_backward64(int nleaves, int k, const NearRow* __restrict__ rows,
+                                                       const NearBlock* __restrict__ blocks,
+                                                       const ST* __restrict__ N, const ST* __restrict__ Vb,
+                                                       const AT* __restrict__ xc, const AT* __restrict__ yhat,
+                                                       AT* __restrict__ yc) {
+  static_assert(64 % G == 0, "groups tile the 64 lanes");
+  __shared__ AT part[4][64];
+  const int l = blockIdx.x;
+  if (l >= nleaves) return;
+  const NearRow d = rows[l];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int r = d.r;
+  const int is = lane < r ? lane : r - 1;  // idle lanes re-read the last row
+  const int mine = d.nb > wave ? (d.nb - wave + 3) / 4 : 0;  // blocks wave, wave + 4, ...
+  NearBlock e{0, 1, 0, 0};
+  if (lane < mine) e = blocks[d.bfirst + wave + 4 * lane];
+  // leaf backward operands: columns n0 .. n0 + nv - 1 of V_tau (a quarter per wave),
+  // the first G of them held in registers until the end
+  const int kq = (k + 3) / 4, n0 = wave * kq;
+  const int nv = min(k, n0 + kq) - n0;  // may be <= 0 for tiny k
+  const ST* Vl = Vb + static_cast<int64_t>(d.b0) * k + static_cast<int64_t>(n0) * r + is;
+  const AT* yh = yhat + static_cast<int64_t>(d.tau) * k + n0;
+  ST va[G];
+  AT yv = 0;
+  if (nv > 0) {
+    yv = yh[min(lane, nv - 1)];
+#pragma unroll
+    for (int u = 0; u < G; ++u) va[u] = Vl[static_cast<int64_t>(min(u, nv - 1)) * r];
+  }
+  const ST* P = N + d.panel_off + is;
+  AT acc = 0;
+  if (mine > 0) {
+    int m = 0, j0 = 0;  // the group issued next: block m, columns j0 .. j0 + G - 1
+    int s0 = __builtin_amdgcn_readlane(e.s0, 0), w = __builtin_amdgcn_readlane(e.w, 0);
+    int cb = __builtin_amdgcn_readlane(e.cb, 0);
+    // stored values stay in the storage type until multiplied, so no conversion
+    // waits for a load ahead of the multiplies
+    auto issue = [&](ST (&a)[G], AT& xv) {
+      xv = xc[s0 + min(lane, w - 1)];
+      const ST* A = P + static_cast<int64_t>(cb) * r;
+#pragma unroll
+      for (int u = 0; u < G; ++u) a[u] = A[static_cast<int64_t>(min(j0 + u, w - 1)) * r];
+    };
+    auto advance = [&]() {
+      j0 += G;
+      if (j0 >= w) {
+        j0 = 0;
+        if (++m < mine) {
+          s0 = __builtin_amdgcn_readlane(e.s0, m);
+          w = __builtin_amdgcn_readlane(e.w, m);
+          cb = __builtin_amdgcn_readlane(e.cb, m);
+        }
+      }
+    };
+    auto mul = [&](const ST (&a)[G], AT xv, int ja, int wa) {
+      const AT xm = lane < wa ? xv : AT(0);
+#pragma unroll
+      for (int u = 0; u < G; ++u) acc += static_cast<AT>(a[u]) * bcast(xm, ja + u);
+    };
+    // two register sets in turn: one is multiplied while the other's loads are in
+    // flight.  Past the last group the issue repeats the last block's first group
+    // (cached); that group gets weight zero, which keeps its loads where they are.
+    ST a[G], b[G];
+    AT xa, xb;
+    int ja = j0, wa = w;
+    issue(a, xa);
+    advance();
+    for (;;) {
+      const int jb = j0, wb = w;
+      const bool endb = m >= mine;
+      issue(b, xb);
+      __builtin_amdgcn_sched_barrier(0);  // the loads go out before the multiplies
+      mul(a, xa, ja, wa);
+      if (endb) {
+        mul(b, xb, 0, 0);
+        break;
+      }
+      advance();
+      ja = j0;
+      wa = w;
+      const bool enda = m >= mine;
+      issue(a, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      mul(b, xb, jb, wb);
+      if (enda) {
+        mul(a, xa, 0, 0);
+        break;
+      }
+      advance();
+    }
+  }
+  // leaf backward: y_tau += V_tau y^_tau over this wave's columns
+  if (nv > 0) {
+    const AT ym = lane < nv ? yv : AT(0);
+#pragma unroll
+    for (int u = 0; u < G; ++u) acc += static_cast<AT>(va[u]) * bcast(ym, u);
+    for (int q0 = G; q0 < nv; q0 += 64) {  // k > 4 G only
+      const AT y2 = q0 + lane < nv ? yh[q0 + lane] : AT(0);
+      acc = stream_dot<ST, AT, 16>(Vl + static_cast<int64_t>(q0) * r, r, min(64, nv - q0), y2, acc);
+    }
+  }
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && lane < r)
+    yc[static_cast<int64_t>(d.b0) + lane] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // ---------------------------------------------------------------- symmetric near field
@@ -1146,31 +1306,49 @@ inline unsigned blocks_for(int64_t work, int per) {
 template <typename ST, typename AT>
 void launch_up(h2_handle_s& H, AT* xh, hipStream_t st) {
   const Structure& S = H.S;
-  for (int l = S.depth - 1; l >= 0; --l) {
+  const ST* E = H.kron ? H.E1.as<ST>() : H.F.as<ST>();
+  const int32_t* list = H.up_list.as<int32_t>();
+  for (int l = S.depth - 1; l >= H.up_top; --l) {
     const int cnt = static_cast<int>(H.up_ptr[l + 1] - H.up_ptr[l]);
     if (cnt == 0) continue;
-    const int32_t* list = H.up_list.as<int32_t>() + H.up_ptr[l];
     if (H.kron)
-      transfer_up_kron<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, list, H.child0.as<int32_t>(),
-                                                                    H.child1.as<int32_t>(), H.E1.as<ST>(), xh);
+      transfer_up<ST, AT, true><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, S.k, list + H.up_ptr[l], H.child0.as<int32_t>(),
+                                                                     H.child1.as<int32_t>(), E, xh);
     else
-      transfer_up<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, S.k, list, H.child0.as<int32_t>(),
-                                                               H.child1.as<int32_t>(), H.F.as<ST>(), xh);
+      transfer_up<ST, AT, false><<<blocks_for(cnt, 4), 256, 0, st>>>(cnt, S.k, list + H.up_ptr[l],
+                                                                      H.child0.as<int32_t>(), H.child1.as<int32_t>(), E,
+                                                                      xh);
+  }
+  if (H.up_top > 0) {
+    if (H.kron)
+      transfer_up_top<ST, AT, true><<<1, 64 * kTopWaves, 0, st>>>(H.up_top, H.up_ptr_dev.as<int64_t>(), S.k, list,
+                                                                  H.child0.as<int32_t>(), H.child1.as<int32_t>(), E, xh);
+    else
+      transfer_up_top<ST, AT, false><<<1, 64 * kTopWaves, 0, st>>>(H.up_top, H.up_ptr_dev.as<int64_t>(), S.k, list,
+                                                                   H.child0.as<int32_t>(), H.child1.as<int32_t>(), E,
+                                                                   xh);
   }
 }
 
 template <typename ST, typename AT>
 void launch_down(h2_handle_s& H, AT* yh, hipStream_t st) {
   const Structure& S = H.S;
-  for (int l = 0; l < S.depth; ++l) {
+  const ST* E = H.kron ? H.E1.as<ST>() : H.ET.as<ST>();
+  if (H.down_top > 0) {
+    if (H.kron)
+      transfer_down_top<ST, AT, true><<<1, 64 * kTopWaves, 0, st>>>(H.down_top, H.level_ptr_dev.as<int32_t>(), S.k,
+                                                                    H.parent.as<int32_t>(), E, yh);
+    else
+      transfer_down_top<ST, AT, false><<<1, 64 * kTopWaves, 0, st>>>(H.down_top, H.level_ptr_dev.as<int32_t>(), S.k,
+                                                                     H.parent.as<int32_t>(), E, yh);
+  }
+  for (int l = H.down_top; l < S.depth; ++l) {
     const int first = S.level_ptr[l + 1], cnt = S.level_ptr[l + 2] - S.level_ptr[l + 1];
     if (cnt == 0) continue;
     if (H.kron)
-      transfer_down_kron<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(),
-                                                                      H.E1.as<ST>(), yh);
+      transfer_down<ST, AT, true><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, S.k, H.parent.as<int32_t>(), E, yh);
     else
-      transfer_down<ST, AT><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, S.k, H.parent.as<int32_t>(),
-                                                                 H.ET.as<ST>(), yh);
+      transfer_down<ST, AT, false><<<blocks_for(cnt, 4), 256, 0, st>>>(first, cnt, S.k, H.parent.as<int32_t>(), E, yh);
   }
 }
 
@@ -1256,10 +1434,15 @@ void matvec_typed(h2_handle_s& H, const XT* x, XT* y, double alpha, hipStream_t 
         n, H.perm.as<int32_t>(), H.leaf_of_pos.as<int32_t>(), H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
         H.near_in_ptr.as<int64_t>(), H.near_in_slot.as<int64_t>(), H.scr_n.as<AT>(), yc, y, alpha, H.overwrite);
   } else {
-    near_backward<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
-                                              H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
-                                              H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
-                                              H.Vb.as<ST>(), xc, yh, yc);
+    if (H.near64)
+      near_backward64<ST, AT, 16><<<nl, 256, 0, st>>>(nl, k, H.near_rows.as<NearRow>(),
+                                                      H.near_blocks.as<NearBlock>(), H.Nmat.as<ST>(), H.Vb.as<ST>(),
+                                                      xc, yh, yc);
+    else
+      near_backward<ST, AT><<<nl, 256, 0, st>>>(nl, k, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                                H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(), H.Nmat.as<ST>(),
+                                                H.Vb.as<ST>(), xc, yh, yc);
     permute_out<XT, AT><<<blocks_for(n, 256), 256, 0, st>>>(n, H.perm.as<int32_t>(), yc, y, alpha, H.overwrite);
   }
   H2_HIP(hipGetLastError());

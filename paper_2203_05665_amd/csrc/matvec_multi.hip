@@ -414,7 +414,56 @@ __device__ inline void load_row64(const float* __restrict__ p, float (&v)[64]) {
   }
 }
 
-// x^_c = E_c0^T x^_c0 + E_c1^T x^_c1 for the parents of one level
+// x^_c = E_c0^T x^_c0 + E_c1^T x^_c1 (lane j < RP: right-hand side j)
+template <int NT>
+__device__ inline void mup_kron(int32_t c, int j, const int32_t* __restrict__ child0,
+                                const int32_t* __restrict__ child1, const float* __restrict__ E1,
+                                float* __restrict__ xhat) {
+  constexpr int RP = 32 * NT;
+  float acc[64];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int64_t ch = __builtin_amdgcn_readfirstlane(a == 0 ? child0[c] : child1[c]);
+    const float* e = E1 + ch * 48;
+    float v[64];
+    load_row64(xhat + (ch * RP + j) * 64, v);
+    kron_axis_regs<0, true>(v, e);
+    kron_axis_regs<1, true>(v, e + 16);
+    kron_axis_regs<2, true>(v, e + 32);
+#pragma unroll
+    for (int i = 0; i < 64; ++i) acc[i] = a == 0 ? v[i] : acc[i] + v[i];
+  }
+  float* out = xhat + (static_cast<int64_t>(c) * RP + j) * 64;
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    *reinterpret_cast<f4v*>(out + 4 * q) = f4v{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+}
+
+// y^_c += E_c y^_parent(c)
+template <int NT>
+__device__ inline void mdown_kron(int64_t c, int j, const int32_t* __restrict__ parent, const float* __restrict__ E1,
+                                  float* __restrict__ yhat) {
+  constexpr int RP = 32 * NT;
+  const int64_t p = __builtin_amdgcn_readfirstlane(parent[c]);
+  const float* e = E1 + c * 48;
+  float v[64];
+  load_row64(yhat + (p * RP + j) * 64, v);
+  kron_axis_regs<0, false>(v, e);
+  kron_axis_regs<1, false>(v, e + 16);
+  kron_axis_regs<2, false>(v, e + 32);
+  float* out = yhat + (c * RP + j) * 64;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    f4v t = ld4c(out + 4 * q);
+    t.x += v[4 * q];
+    t.y += v[4 * q + 1];
+    t.z += v[4 * q + 2];
+    t.w += v[4 * q + 3];
+    *reinterpret_cast<f4v*>(out + 4 * q) = t;
+  }
+}
+
+// the parents of one level, one wave each
 template <int NT>
 __global__ __launch_bounds__(256) void mtransfer_up_kron(int count, const int32_t* __restrict__ list,
                                                          const int32_t* __restrict__ child0,
@@ -445,32 +494,44 @@ __global__ __launch_bounds__(256) void mtransfer_up_kron(int count, const int32_
     *reinterpret_cast<f4v*>(out + 4 * q) = f4v{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
 }
 
-// y^_c += E_c y^_parent(c) for the clusters of one level
+// the clusters of one level, one wave each
 template <int NT>
 __global__ __launch_bounds__(256) void mtransfer_down_kron(int first, int count, const int32_t* __restrict__ parent,
                                                            const float* __restrict__ E1, float* __restrict__ yhat) {
   const int it = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_item(count)));
   if (it >= count) return;  // uniform per wave
-  constexpr int RP = 32 * NT;
   const int j = threadIdx.x % 64;
-  if (j >= RP) return;
-  const int64_t c = first + it;
-  const int64_t p = __builtin_amdgcn_readfirstlane(parent[c]);
-  const float* e = E1 + c * 48;
-  float v[64];
-  load_row64(yhat + (p * RP + j) * 64, v);
-  kron_axis_regs<0, false>(v, e);
-  kron_axis_regs<1, false>(v, e + 16);
-  kron_axis_regs<2, false>(v, e + 32);
-  float* out = yhat + (c * RP + j) * 64;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    f4v t = ld4c(out + 4 * q);
-    t.x += v[4 * q];
-    t.y += v[4 * q + 1];
-    t.z += v[4 * q + 2];
-    t.w += v[4 * q + 3];
-    *reinterpret_cast<f4v*>(out + 4 * q) = t;
+  if (j >= 32 * NT) return;
+  mdown_kron<NT>(first + it, j, parent, E1, yhat);
+}
+
+// The top levels (few clusters each) in one workgroup of 8 waves, level by level
+// with a workgroup barrier between levels, as for one right-hand side.
+constexpr int kMTopWaves = 8;
+
+template <int NT>
+__global__ __launch_bounds__(64 * kMTopWaves) void mtransfer_up_kron_top(
+    int nlev, const int64_t* __restrict__ lev, const int32_t* __restrict__ list, const int32_t* __restrict__ child0,
+    const int32_t* __restrict__ child1, const float* __restrict__ E1, float* __restrict__ xhat) {
+  const int wave = threadIdx.x / 64, j = threadIdx.x % 64;
+  for (int l = nlev - 1; l >= 0; --l) {
+    if (j < 32 * NT)
+      for (int64_t w = lev[l] + wave; w < lev[l + 1]; w += kMTopWaves)
+        mup_kron<NT>(__builtin_amdgcn_readfirstlane(list[w]), j, child0, child1, E1, xhat);
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(64 * kMTopWaves) void mtransfer_down_kron_top(int nlev, const int32_t* __restrict__ level_ptr,
+                                                                           const int32_t* __restrict__ parent,
+                                                                           const float* __restrict__ E1,
+                                                                           float* __restrict__ yhat) {
+  const int wave = threadIdx.x / 64, j = threadIdx.x % 64;
+  for (int l = 0; l < nlev; ++l) {
+    if (j < 32 * NT)
+      for (int64_t c = level_ptr[l + 1] + wave; c < level_ptr[l + 2]; c += kMTopWaves) mdown_kron<NT>(c, j, parent, E1, yhat);
+    __syncthreads();
   }
 }
 
@@ -979,14 +1040,37 @@ std::vector<int32_t> balanced_rows(const Structure& S) {
   return order;
 }
 
-// row clusters in XCD chunks of equal admissible-block count (built on first use)
+// Row clusters in their natural order, four per workgroup, so that workgroup g
+// (on XCD g mod 8) takes rows 4g..4g+3: neighbouring rows run at the same time on
+// all eight XCDs instead of in eight separate ranges.
+std::vector<int32_t> interleaved_rows(const Structure& S) {
+  const int64_t nc = S.nclusters;
+  const int64_t nit = (nc + 31) / 32 * 32, nwg = nit / 4, per = nwg / 8;
+  std::vector<int32_t> order(nit, -1);
+  for (int64_t g = 0; g < nwg; ++g)
+    for (int w = 0; w < 4; ++w) {
+      const int64_t row = 4 * g + w;
+      order[((g % 8) * per + g / 8) * 4 + w] = row < nc ? static_cast<int32_t>(row) : -1;
+    }
+  return order;
+}
+
+}  // namespace
+
+// the row order of the coupling kernels (built on first use, rebuilt when the
+// row-order knob changes): XCD chunks of equal admissible-block count, or
+// interleaved
 void ensure_row_order(h2_handle_s& H) {
-  if (H.morder.p == nullptr) {
-    const std::vector<int32_t> ord = balanced_rows(H.S);
+  const int kind = H.tune_order == 2 ? 2 : 1;
+  if (H.morder.p == nullptr || H.morder_kind != kind) {
+    const std::vector<int32_t> ord = kind == 2 ? interleaved_rows(H.S) : balanced_rows(H.S);
     H.morder.upload(ord);
     H.morder_items = static_cast<int64_t>(ord.size());
+    H.morder_kind = kind;
   }
 }
+
+namespace {
 
 template <int NT, typename XT>
 void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t ldy, double alpha, hipStream_t st) {
@@ -1013,7 +1097,8 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
   mpermute_in<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), x, ldx, xc);
   mleaf_forward<NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                                H.cend.as<int32_t>(), H.Vf.as<float>(), xc, xh);
-  for (int lv = S.depth - 1; lv >= 0; --lv) {
+  const int up_top = H.kron ? H.mup_top : 0;  // the dense MFMA transfers run one launch per level
+  for (int lv = S.depth - 1; lv >= up_top; --lv) {
     const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
     if (cnt == 0) continue;
     if (H.kron)
@@ -1024,6 +1109,10 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
       mtransfer_up<NT><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
                                                    H.child0.as<int32_t>(), H.child1.as<int32_t>(), H.ET.as<float>(), xh);
   }
+  if (up_top > 0)
+    mtransfer_up_kron_top<NT><<<1, 64 * kMTopWaves, 0, st>>>(up_top, H.up_ptr_dev.as<int64_t>(),
+                                                             H.up_list.as<int32_t>(), H.child0.as<int32_t>(),
+                                                             H.child1.as<int32_t>(), H.E1.as<float>(), xh);
   if (H.prof) {
     e1 = prof_event(H);
     H2_HIP(hipEventRecord(e1, st));
@@ -1056,7 +1145,11 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     e2 = prof_event(H);
     H2_HIP(hipEventRecord(e2, st));
   }
-  for (int lv = 0; lv < S.depth; ++lv) {
+  const int down_top = H.kron ? H.mdown_top : 0;
+  if (down_top > 0)
+    mtransfer_down_kron_top<NT><<<1, 64 * kMTopWaves, 0, st>>>(down_top, H.level_ptr_dev.as<int32_t>(),
+                                                               H.parent.as<int32_t>(), H.E1.as<float>(), yh);
+  for (int lv = down_top; lv < S.depth; ++lv) {
     const int first = S.level_ptr[lv + 1], cnt = S.level_ptr[lv + 2] - S.level_ptr[lv + 1];
     if (cnt == 0) continue;
     if (H.kron)
@@ -1185,7 +1278,8 @@ static int pass_columns(const h2_handle_s& H, int nrhs, int dtype) {
 bool matvec_multi_ready(const h2_handle_s& H, int nrhs, int dtype) {
   const int rp = pass_columns(H, nrhs, dtype);
   const size_t need_v = static_cast<size_t>(H.S.n) * rp * 4, need_h = static_cast<size_t>(H.S.nclusters) * 64 * rp * 4;
-  return H.mxc.bytes >= need_v && H.mxhat.bytes >= need_h && H.morder.p != nullptr;
+  return H.mxc.bytes >= need_v && H.mxhat.bytes >= need_h && H.morder.p != nullptr &&
+         H.morder_kind == (H.tune_order == 2 ? 2 : 1);
 }
 
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,

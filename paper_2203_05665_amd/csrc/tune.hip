@@ -28,7 +28,18 @@ int applicable_knob(const h2_handle_s& H, int nrhs, int dtype) {
   return H2_TUNE_NONE;
 }
 
-int& knob_ref(h2_handle_s& H, int knob) { return knob == H2_TUNE_PASS_COLUMNS ? H.tune_pass : H.tune_slot; }
+int& knob_ref(h2_handle_s& H, int knob) {
+  return knob == H2_TUNE_PASS_COLUMNS ? H.tune_pass : knob == H2_TUNE_ROW_ORDER ? H.tune_order : H.tune_slot;
+}
+
+// the knobs the path of (nrhs, dtype) has, and their values
+std::vector<int> knob_values(const h2_handle_s& H, int knob, int nrhs, int dtype) {
+  const bool cx = dtype == H2_C128 || dtype == H2_C64;
+  if (knob == H2_TUNE_PASS_COLUMNS && !cx && nrhs >= 2 && matvec_multi_supported(H)) return {32, 64};
+  if (knob == H2_TUNE_ROW_ORDER && nrhs >= 2 && matvec_multi_supported(H)) return {1, 2};
+  if (knob == H2_TUNE_SMALL_SLOT && applicable_knob(H, nrhs, dtype) == H2_TUNE_SMALL_SLOT) return {16, 32};
+  return {};
+}
 
 struct Events {
   hipEvent_t a = nullptr, b = nullptr;
@@ -52,29 +63,43 @@ void set_tuning(h2_handle_s& H, int knob, int value) {
     if (value != 0 && value != 16 && value != 32) throw Error(H2_EINVAL, "H2_TUNE_SMALL_SLOT takes 0, 16 or 32");
     if (value == 16 && H.S.k > 16) throw Error(H2_EINVAL, "slots of 16 lanes need k <= 16");
     H.tune_slot = value;
+  } else if (knob == H2_TUNE_ROW_ORDER) {
+    if (value != 0 && value != 1 && value != 2) throw Error(H2_EINVAL, "H2_TUNE_ROW_ORDER takes 0, 1 or 2");
+    H.tune_order = value;
+    // a row order already in use is rebuilt now, not in a later product
+    if (H.morder.p != nullptr) ensure_row_order(H);
   } else {
     throw Error(H2_EINVAL, "unknown tuning knob");
   }
 }
 
-void tune(h2_handle_s& H, int nrhs, int dtype, int reps, h2_tune_info& info, hipStream_t st) {
+void tune(h2_handle_s& H, int nrhs, int dtype, int reps, h2_tune_info& info, hipStream_t st, int which) {
   if (H.host_only) throw Error(H2_EINVAL, "handle was built with H2_HOST_ONLY");
   if (nrhs < 1) throw Error(H2_EINVAL, "nrhs must be >= 1");
   if (reps < 1 || reps > 1000) throw Error(H2_EINVAL, "reps must be in 1..1000");
   if (dtype != H2_R64 && dtype != H2_R32 && dtype != H2_C128 && dtype != H2_C64)
     throw Error(H2_EINVAL, "unknown dtype");
+  if (which != -2 && which != H2_TUNE_PASS_COLUMNS && which != H2_TUNE_SMALL_SLOT && which != H2_TUNE_ROW_ORDER)
+    throw Error(H2_EINVAL, "unknown tuning knob");
   info = h2_tune_info{};
-  info.knob = applicable_knob(H, nrhs, dtype);
+  info.knob = which == -2 ? applicable_knob(H, nrhs, dtype) : which;
   if (info.knob == H2_TUNE_NONE) return;
-  const std::vector<int> values = info.knob == H2_TUNE_PASS_COLUMNS ? std::vector<int>{32, 64}
-                                                                    : std::vector<int>{16, 32};
-  const int64_t n = H.S.n, count = n * nrhs;  // real vectors only from here on
-  const size_t es = dtype == H2_R64 ? 8 : 4;
+  const std::vector<int> values = knob_values(H, info.knob, nrhs, dtype);
+  if (values.empty()) {
+    info.knob = H2_TUNE_NONE;
+    return;
+  }
+
+  // trial vectors: n x nrhs entries, complex ones as interleaved pairs of scalars
+  const int cw = (dtype == H2_C128 || dtype == H2_C64) ? 2 : 1;
+  const bool dbl = dtype == H2_R64 || dtype == H2_C128;
+  const int64_t n = H.S.n, count = n * nrhs * cw;
+  const size_t es = dbl ? 8 : 4;
   DBuf xb, yb;
-  xb.alloc(static_cast<size_t>(n) * nrhs * es);
-  yb.alloc(static_cast<size_t>(n) * nrhs * es);
+  xb.alloc(static_cast<size_t>(count) * es);
+  yb.alloc(static_cast<size_t>(count) * es);
   const unsigned g = static_cast<unsigned>((count + 255) / 256);
-  if (dtype == H2_R32) tune_fill<float><<<g, 256, 0, st>>>(count, xb.as<float>());
+  if (!dbl) tune_fill<float><<<g, 256, 0, st>>>(count, xb.as<float>());
   else tune_fill<double><<<g, 256, 0, st>>>(count, xb.as<double>());
   H2_HIP(hipGetLastError());
   H2_HIP(hipMemsetAsync(yb.p, 0, yb.bytes, st));

@@ -29,8 +29,8 @@ H2_CG, H2_GMRES = 0, 1
 (H2_X_PERM, H2_X_CLUSTERS, H2_X_BOXES, H2_X_ADM, H2_X_NEAR, H2_X_DFS, H2_X_V, H2_X_E, H2_X_S,
  H2_X_N) = range(10)
 H2_PH_FORWARD, H2_PH_COUPLING, H2_PH_DOWN, H2_PH_NEAR, H2_PH_TOTAL, H2_NPHASE = 0, 1, 2, 3, 4, 5
-H2_TUNE_NONE, H2_TUNE_PASS_COLUMNS, H2_TUNE_SMALL_SLOT = -1, 0, 1
-TUNE_KNOBS = {"pass_columns": H2_TUNE_PASS_COLUMNS, "small_slot": H2_TUNE_SMALL_SLOT}
+H2_TUNE_NONE, H2_TUNE_PASS_COLUMNS, H2_TUNE_SMALL_SLOT, H2_TUNE_ROW_ORDER = -1, 0, 1, 2
+TUNE_KNOBS = {"pass_columns": H2_TUNE_PASS_COLUMNS, "small_slot": H2_TUNE_SMALL_SLOT, "row_order": H2_TUNE_ROW_ORDER}
 
 KERNELS = {"laplace": H2_LAPLACE, "helmholtz": H2_HELMHOLTZ, "one": H2_TEST_ONE,
            "bilinear": H2_TEST_BILINEAR, "quadratic": H2_TEST_QUADRATIC}
@@ -110,7 +110,7 @@ def lib():
         L.h2_krylov_solution.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.h2_krylov_destroy.argtypes = [C.c_void_p]
         L.h2_krylov_destroy.restype = None
-        L.h2_stream_read.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        L.h2_stream_read.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_int64, C.c_void_p]
         L.h2_info.argtypes = [C.c_void_p, C.POINTER(h2_stats)]
         L.h2_free.argtypes = [C.c_void_p]
         L.h2_free.restype = None
@@ -125,10 +125,12 @@ def lib():
         L.h2_recompress.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(h2_recompress_info), C.c_void_p]
         L.h2_tune.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(h2_tune_info), C.c_void_p]
         L.h2_set_tuning.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.h2_tune_knob.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(h2_tune_info),
+                                   C.c_void_p]
         for f in ("build_h2", "h2_matvec", "h2_solve", "h2_solve_noalloc", "h2_info", "h2_export", "h2_profile", "h2_profile_read",
                   "h2_krylov_dots", "h2_krylov_update", "h2_recompress", "h2_tune", "h2_set_tuning",
                   "h2_krylov_create", "h2_krylov_begin", "h2_krylov_next", "h2_krylov_advance", "h2_krylov_poll",
-                  "h2_krylov_residuals", "h2_krylov_solution", "h2_stream_read"):
+                  "h2_krylov_residuals", "h2_krylov_solution", "h2_stream_read", "h2_tune_knob"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -354,10 +356,11 @@ def h2_krylov_update(Q, h, W, sign=1.0, stream=None):
     return W
 
 
-def h2_stream_read(buf, sink, stream=None):
+def h2_stream_read(buf, sink, loads=8, stream=None):
     """Launch the read-only streaming kernel over the bytes of device tensor `buf`
-    (sink: a device tensor of at least 32 KiB)."""
-    _check(lib().h2_stream_read(buf.data_ptr(), buf.numel() * buf.element_size(), sink.data_ptr(),
+    with `loads` (4, 8, 16) loads in flight per thread (sink: a device tensor of
+    at least 16 KiB)."""
+    _check(lib().h2_stream_read(buf.data_ptr(), buf.numel() * buf.element_size(), int(loads), sink.data_ptr(),
                                 sink.numel() * sink.element_size(), _stream(stream)))
 
 
@@ -369,14 +372,18 @@ def h2_recompress(h, eps, max_rank=0, stream=None) -> dict:
     return {f: getattr(info, f) for f, _ in h2_recompress_info._fields_}
 
 
-def h2_tune(h, nrhs=1, dtype="f64", reps=10, stream=None) -> dict:
+def h2_tune(h, nrhs=1, dtype="f64", reps=10, stream=None, knob=None) -> dict:
     """Time every tile choice of the product path for nrhs columns of the given
-    vector type ("f64" or "f32") on the handle and keep the fastest (see h2_tune
-    in include/h2.h); returns the knob, the values tried, their median ms and the
-    value kept."""
+    vector type ("f64", "f32", "c128", "c64") on the handle and keep the fastest
+    (see h2_tune in include/h2.h; `knob` names one knob, h2_tune_knob); returns
+    the knob, the values tried, their median ms and the value kept."""
     dt = {"f64": H2_R64, "f32": H2_R32, "c128": H2_C128, "c64": H2_C64}[dtype]
     info = h2_tune_info()
-    _check(lib().h2_tune(h, int(nrhs), dt, int(reps), C.byref(info), _stream(stream)))
+    if knob is None:
+        _check(lib().h2_tune(h, int(nrhs), dt, int(reps), C.byref(info), _stream(stream)))
+    else:
+        _check(lib().h2_tune_knob(h, TUNE_KNOBS[knob] if isinstance(knob, str) else int(knob), int(nrhs), dt,
+                                  int(reps), C.byref(info), _stream(stream)))
     names = {v: k for k, v in TUNE_KNOBS.items()}
     vals = [info.value[i] for i in range(info.ncand)]
     return {"knob": names.get(info.knob), "values": vals, "ms": [info.ms[i] for i in range(info.ncand)],
@@ -449,9 +456,9 @@ class H2Matrix:
         self.info = h2_info(self.h)
         return out
 
-    def tune(self, nrhs=1, dtype="f64", reps=10, stream=None):
+    def tune(self, nrhs=1, dtype="f64", reps=10, stream=None, knob=None):
         """Pick the fastest tile shapes for products with nrhs columns (see h2_tune)."""
-        return h2_tune(self.h, nrhs, dtype, reps, stream)
+        return h2_tune(self.h, nrhs, dtype, reps, stream, knob)
 
     def set_tuning(self, knob, value):
         h2_set_tuning(self.h, knob, value)

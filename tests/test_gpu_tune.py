@@ -119,3 +119,39 @@ def test_paths_without_alternatives():
     finally:
         A.close()
     assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "helmholtz"])
+def test_row_order_every_value_matches_oracle(kernel):
+    """Many right-hand sides: both row orders of the coupling kernels (XCD chunks,
+    interleaved) give the oracle's product, and h2_tune_knob times both and keeps
+    one."""
+    from oracle.kernels import HELMHOLTZ, LAPLACE
+    kind, level, m, leaf = "sphere", 3, 4, 64
+    V, T = I.mesh_for(kind, level)
+    cx = kernel == "helmholtz"
+    H = H2Oracle(V, T, Kernel(HELMHOLTZ if cx else LAPLACE, 2.0 if cx else 0.0), m=m, leaf=leaf, eta=0.5)
+    L = oracle(kind, level, m, leaf)
+    n, nrhs = H.mesh.n, 20
+    rng = np.random.default_rng(61)
+    X = rng.standard_normal((n, nrhs)) + (1j * rng.standard_normal((n, nrhs)) if cx else 0)
+    A = h2.H2Matrix(V, T, kernel=kernel, kappa=2.0 if cx else 0.0, order=m, leaf=leaf, eta=0.5, storage="f32")
+    try:
+        out = {}
+        for v in (1, 2):
+            A.set_tuning("row_order", v)
+            xd = torch.tensor(np.ascontiguousarray(X.T), device="cuda").t()
+            yd = torch.zeros_like(xd)
+            A.matvec(xd, yd)
+            torch.cuda.synchronize()
+            out[v] = yd.cpu().numpy()
+        info = A.tune(nrhs, "c128" if cx else "f64", reps=3, knob="row_order")
+    finally:
+        A.close()
+    print("row order tuning (%s):" % kernel, info)
+    assert info["knob"] == "row_order" and info["values"] == [1, 2] and info["chosen"] in (1, 2)
+    for v, Y in out.items():
+        for j in range(nrhs):
+            ref = H.matvec(X[:, j])
+            scale = L.matvec(np.abs(X[:, j]))
+            bounds.check(Y[:, j], ref, scale, "f32", "row order %d %s col %d" % (v, kernel, j))

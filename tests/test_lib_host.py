@@ -156,7 +156,10 @@ def test_tuning_argument_errors():
         h2.h2_set_tuning(h, "pass_columns", 64)
         h2.h2_set_tuning(h, "pass_columns", 0)
         h2.h2_set_tuning(h, "small_slot", 32)
-        for knob, value in (("pass_columns", 48), ("small_slot", 8), ("small_slot", 16), (7, 32), (-1, 0)):
+        for v in (1, 2, 0):
+            h2.h2_set_tuning(h, "row_order", v)
+        for knob, value in (("pass_columns", 48), ("small_slot", 8), ("small_slot", 16), (7, 32), (-1, 0),
+                            ("row_order", 3), ("row_order", -1)):
             with pytest.raises(h2.H2Error) as e:
                 h2.h2_set_tuning(h, knob, value)
             assert e.value.code == h2.H2_EINVAL
@@ -174,6 +177,7 @@ def test_tuning_argument_errors():
     info = h2.h2_tune_info()
     assert L.h2_tune(None, 1, h2.H2_R64, 5, ctypes.byref(info), None) == h2.H2_EINVAL
     assert L.h2_set_tuning(None, 0, 0) == h2.H2_EINVAL
+    assert L.h2_tune_knob(None, h2.H2_TUNE_ROW_ORDER, 2, h2.H2_R64, 5, ctypes.byref(info), None) == h2.H2_EINVAL
 
 
 def test_symmetric_near_field_only():
