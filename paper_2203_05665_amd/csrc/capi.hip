@@ -145,7 +145,7 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
         {
           std::vector<h2::NearRow> rows(S.leaves.size());
           std::vector<h2::NearBlock> blks(S.near_col.size());
-          bool fits = true;
+          bool fits = true, fits64 = true;
           for (size_t l = 0; l < S.leaves.size(); ++l) {
             const int32_t tau = S.leaves[l];
             const int64_t nb = S.near_ptr[l + 1] - S.near_ptr[l];
@@ -158,10 +158,12 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
               c += w;
             }
             fits = fits && rows[l].r <= 64 && nb <= 256;
+            fits64 = fits64 && rows[l].r <= 64 && nb <= 64;
           }
           H->near_rows.upload(rows);
           H->near_blocks.upload(blks);
           H->near64 = fits;
+          H->near_row64 = fits64;
         }
         std::vector<int32_t> ul;
         H->up_ptr.assign(S.depth + 1, 0);

@@ -92,6 +92,7 @@ struct h2_handle_s {
   // near blocks, so that kernel applies
   h2::DBuf near_rows, near_blocks;
   bool near64 = false;
+  bool near_row64 = false;  // also at most 64 near blocks per row (mnear_stream16 applies)
   // on-the-fly coupling: cluster centres (FP64, 3 per cluster) and point offsets from
   // the centre (3 x m per cluster, FP32 and FP64)
   h2::DBuf ctr, off32, off64;
@@ -124,8 +125,13 @@ struct h2_handle_s {
   // tile choices (0: the built-in rule), set by h2_tune or h2_set_tuning
   int tune_pass = 0;  // right-hand sides per many-RHS pass: 32 or 64
   int tune_slot = 0;  // lanes per block-row slot of the small-k coupling: 16 or 32
-  int tune_order = 0; // row order of the many-RHS coupling: 1 XCD chunks, 2 interleaved (0: rule, 1)
-  int morder_kind = 0;  // the order morder holds
+  int tune_order = 0; // schedule of the many-RHS coupling: 1 XCD chunks, 2 interleaved,
+                      // 3 row groups sharing x^ (0: rule, 1)
+  int morder_kind = 0;  // the schedule morder (and the groups) hold
+  // schedule 3: row groups (4 cluster ids each, -1 unused), their entry ranges and
+  // entries (column cluster, the block of each of the 4 rows or -1, 3 x padding)
+  h2::DBuf mgrp_rows, mgrp_ptr, mgrp_tasks;
+  int64_t mgrp_n = 0;
   bool overwrite = false;  // the current product assigns y <- alpha G~ x (H2_OVERWRITE)
   // h2_solve: the Krylov solver's workspace and its pinned status (kept between
   // calls, grown when a call needs more)

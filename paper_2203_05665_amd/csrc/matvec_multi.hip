@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <vector>
 
 #include "handle.h"
@@ -255,6 +256,116 @@ __global__ __launch_bounds__(256) void mcoupling(int64_t nitems, const int32_t* 
   for (int64_t b = ptr[tau]; b < b1; ++b)
     mma64_rowA<NT>(S + b * 4096, xhat + static_cast<int64_t>(col[b]) * RP * 64, acc);
   store_hat<NT, false>(yhat + tau * RP * 64, acc);
+}
+
+// y^_tau = sum_sigma S_{tau sigma} x^_sigma for four row clusters per workgroup
+// (64 right-hand sides), so that x^_sigma, which the rows of a group share, is
+// read from HBM once per group instead of once per row.  A group is usually the
+// four grandchildren of one cluster: neighbours whose admissible lists overlap
+// (Algorithm 3 visits the same sigma from each of them).  Its work is the union
+// of the four lists, ordered by column cluster; an entry holds sigma and the block
+// S_{tau sigma} of each slot (-1 where tau does not meet sigma), so every row meets
+// its blocks in the order of its own list.  Each (entry, slot) with a block is a
+// task: the workgroup stages S_{tau sigma} (and x^_sigma when sigma changes) into
+// LDS with contiguous 16-byte loads, one task ahead, and each wave multiplies its
+// 32 x 32 tile (rows 32 ti of S, right-hand sides 32 tj) into that slot's
+// accumulator: the four waves share every task, so none waits for a row it does
+// not own.  The K order per block is that of mma64_rowA, so every tile sums the
+// same products in the same order as mcoupling.
+constexpr int kGrpPitch = 68;  // LDS row pitch in floats: 16-byte reads of 16 lanes cover all 64 banks
+
+__device__ inline void mma_tile_k64(const float* __restrict__ As, const float* __restrict__ Bs, f32x16& acc) {
+  f4v a[8], b[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    a[p] = *reinterpret_cast<const f4v*>(As + 8 * p);
+    b[p] = *reinterpret_cast<const f4v*>(Bs + 8 * p);
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc = mfma(a[p][e], b[p][e], acc);
+}
+
+__global__ __launch_bounds__(256) void mcoupling_grp(int64_t ngroups, const int32_t* __restrict__ grows,
+                                                     const int64_t* __restrict__ gent,
+                                                     const int32_t* __restrict__ ents, const float* __restrict__ S,
+                                                     const float* __restrict__ xhat, float* __restrict__ yhat) {
+  constexpr int RP = 64;
+  __shared__ __align__(16) float sbuf[2][64 * kGrpPitch];
+  __shared__ __align__(16) float xbuf[2][64 * kGrpPitch];
+  const int64_t per = gridDim.x / 8;  // groups per XCD chunk (the grid is 8 chunks)
+  const int64_t g = static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (g >= ngroups) return;  // whole workgroup
+  const int t = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(t / 64), l = t % 64, r = l % 32, h = l / 32;
+  const int ti = wave >> 1, tj = wave & 1;
+  const int64_t e0 = gent[g], e1 = gent[g + 1];
+  f32x16 acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+  // staging: 16 KB tiles (64 rows of 64 floats), thread t moves vectors q 256 + t
+  f4v sreg[4], xreg[4];
+  auto fetch = [&](const float* src, f4v(&reg)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reg[q] = ld4c(src + (q * 256 + t) * 4);
+  };
+  auto put = [&](float* dst, const f4v(&reg)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = (q * 256 + t) * 4;
+      *reinterpret_cast<f4v*>(dst + (f / 64) * kGrpPitch + f % 64) = reg[q];
+    }
+  };
+  // entry e: ents[8 e] = sigma, ents[8 e + 1 + i] = block of slot i or -1
+  auto first_block = [&](int64_t e) {
+    const int32_t* en = ents + 8 * e;
+    return en[1] >= 0 ? en[1] : en[2] >= 0 ? en[2] : en[3] >= 0 ? en[3] : en[4];
+  };
+  if (e0 < e1) {
+    fetch(S + static_cast<int64_t>(first_block(e0)) * 4096, sreg);
+    fetch(xhat + static_cast<int64_t>(ents[8 * e0]) * RP * 64, xreg);
+    put(sbuf[0], sreg);
+    put(xbuf[0], xreg);
+  }
+  __syncthreads();
+  int sc = 0, xcur = 0;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int32_t* en = ents + 8 * e;
+    const int32_t blk[4] = {en[1], en[2], en[3], en[4]};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (blk[i] >= 0) {
+        // the next task: a later slot of this entry, else the first of the next entry
+        int32_t nb = -1;
+#pragma unroll
+        for (int j = 3; j > i; --j)
+          if (blk[j] >= 0) nb = blk[j];
+        const bool newx = nb < 0 && e + 1 < e1;
+        if (newx) nb = first_block(e + 1);
+        if (nb >= 0) fetch(S + static_cast<int64_t>(nb) * 4096, sreg);
+        if (newx) fetch(xhat + static_cast<int64_t>(ents[8 * e + 8]) * RP * 64, xreg);
+        mma_tile_k64(sbuf[sc] + (32 * ti + r) * kGrpPitch + 4 * h, xbuf[xcur] + (32 * tj + r) * kGrpPitch + 4 * h,
+                     acc[i]);
+        if (nb >= 0) put(sbuf[sc ^ 1], sreg);
+        if (newx) put(xbuf[xcur ^ 1], xreg);
+        __syncthreads();
+        sc ^= 1;
+        if (newx) xcur ^= 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int32_t tau = grows[4 * g + i];
+    if (tau >= 0) {
+      float* out = yhat + static_cast<int64_t>(tau) * RP * 64;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) out[(32 * tj + r) * 64 + 32 * ti + acc_row(v, l)] = acc[i][v];
+    }
+  }
 }
 
 // The same with S evaluated on the fly (eq. coupling): every lane computes the
@@ -646,6 +757,119 @@ __device__ inline void near16_leaf(int64_t it, int r, int64_t b0, int32_t tau, c
         const int i = 16 * ti + 4 * lk + v;
         if (i < r) out[i * RP + 16 * tj] = acc[ti][tj][v];
       }
+}
+
+// The same product with the K-steps of all the row's near blocks in one stream,
+// for rows of at most 64 near blocks: the wave holds the blocks' descriptors
+// (first triangle s0 and width w of sigma, first panel column cb) one per lane and
+// keeps NP K-steps in flight across block boundaries, so the pipeline never
+// drains between blocks.  A K-step past a block's last column re-reads that
+// column of the panel and multiplies it by a row of zeros instead of x, so no
+// loaded value needs a mask.
+__device__ float kZeroRow[64];  // zero-initialised, never written
+
+template <int TJ, int NTI>
+__device__ inline void near16_stream(const NearRow& d, const NearBlock* __restrict__ blocks, const float* __restrict__ N,
+                                     const float* __restrict__ Vb, const float* __restrict__ xc,
+                                     const float* __restrict__ yhat, float* __restrict__ yc) {
+  constexpr int RP = 16 * TJ;
+  constexpr int NP = TJ >= 4 ? 3 : 4;  // K-steps in flight (within 128 VGPRs: four waves per SIMD)
+  const int l = threadIdx.x % 64, li = l % 16, lk = l / 16;
+  const int r = d.r;
+  int rowc[NTI];
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti) rowc[ti] = min(16 * ti + li, r - 1);  // rows past r are computed, not stored
+  f4v acc[NTI][TJ];
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = f4v{0.f, 0.f, 0.f, 0.f};
+  NearBlock e{0, 1, 0, 0};
+  if (l < d.nb) e = blocks[d.bfirst + l];
+  int nst = l < d.nb ? (e.w + 3) >> 2 : 0;  // K-steps of the whole row
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nst += __shfl_xor(nst, o);
+  nst = __builtin_amdgcn_readfirstlane(nst);
+  const float* P = N + d.panel_off;
+  int m = 0, k0 = 0;  // the K-step fetched next: block m, columns k0 .. k0 + 3
+  int s0 = __builtin_amdgcn_readlane(e.s0, 0), w = __builtin_amdgcn_readlane(e.w, 0);
+  int cb = __builtin_amdgcn_readlane(e.cb, 0);
+  auto fetch = [&](float (&av)[NTI], float (&bv)[TJ]) {
+    const int kk = k0 + lk;
+    const int kc = min(kk, w - 1);
+    const float* B = (m < d.nb && kk < w) ? xc + static_cast<int64_t>(s0 + kk) * RP + li : kZeroRow + li;
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) bv[tj] = B[16 * tj];
+    const float* A = P + static_cast<int64_t>(cb + kc) * r;
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti) av[ti] = A[rowc[ti]];
+    k0 += 4;
+    if (k0 >= w) {
+      k0 = 0;
+      if (++m < d.nb) {  // past the last block the last one is re-read, times zero
+        s0 = __builtin_amdgcn_readlane(e.s0, m);
+        w = __builtin_amdgcn_readlane(e.w, m);
+        cb = __builtin_amdgcn_readlane(e.cb, m);
+      }
+    }
+  };
+  // whole rounds of NP steps: the steps past the row's last one multiply zeros, so
+  // every round is the same straight-line code and the loads stay NP steps ahead
+  float av[NP][NTI], bv[NP][TJ];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) fetch(av[q], bv[q]);
+  for (int st = 0; st < nst; st += NP) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = mfma16(av[q][ti], bv[q][tj], acc[ti][tj]);
+      fetch(av[q], bv[q]);
+    }
+  }
+  // + V_tau y^_tau: A = Vb (column-major r x 64), B(kk, j) = y^_tau[j * 64 + kk]
+  const float* A = Vb + static_cast<int64_t>(d.b0) * 64;
+  const float* Y = yhat + static_cast<int64_t>(d.tau) * RP * 64 + li * 64;
+#pragma unroll 2
+  for (int q0 = 0; q0 < 64; q0 += 4) {
+    const int kk = q0 + lk;
+    float a2[NTI], b2[TJ];
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) b2[tj] = Y[16 * tj * 64 + kk];
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti) a2[ti] = A[kk * r + rowc[ti]];
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = mfma16(a2[ti], b2[tj], acc[ti][tj]);
+  }
+  float* out = yc + static_cast<int64_t>(d.b0) * RP + li;
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * ti + 4 * lk + v;
+        if (i < r) out[i * RP + 16 * tj] = acc[ti][tj][v];
+      }
+}
+
+template <int TJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mnear_stream16(
+    int nleaves, const NearRow* __restrict__ rows, const NearBlock* __restrict__ blocks, const float* __restrict__ N,
+    const float* __restrict__ Vb, const float* __restrict__ xc, const float* __restrict__ yhat,
+    float* __restrict__ yc) {
+  const int64_t it = xcd_item(nleaves);
+  if (it >= nleaves) return;
+  const NearRow d = rows[it];
+  switch ((d.r + 15) >> 4) {  // wave-uniform: one leaf per wave
+    case 1: near16_stream<TJ, 1>(d, blocks, N, Vb, xc, yhat, yc); break;
+    case 2: near16_stream<TJ, 2>(d, blocks, N, Vb, xc, yhat, yc); break;
+    case 3: near16_stream<TJ, 3>(d, blocks, N, Vb, xc, yhat, yc); break;
+    default: near16_stream<TJ, 4>(d, blocks, N, Vb, xc, yhat, yc); break;
+  }
 }
 
 template <int TJ>
@@ -1055,17 +1279,105 @@ std::vector<int32_t> interleaved_rows(const Structure& S) {
   return order;
 }
 
+// The groups of mcoupling_grp: the four grandchildren of every cluster whose two
+// children both have children, then the remaining row clusters in runs of up to
+// four consecutive ids; sorted by first row, cut into 8 contiguous chunks of about
+// equal work (blocks + 1 per group), one per XCD, each padded with empty groups to
+// the common length.  Entries: (column cluster, block of each slot or -1, 3 x
+// padding), per group ordered by the position of the column cluster.
+void build_groups(h2_handle_s& H) {
+  const Structure& S = H.S;
+  const int32_t nc = S.nclusters;
+  std::vector<std::array<int32_t, 4>> groups;
+  std::vector<char> done(nc, 0);
+  for (int32_t p = 0; p < nc; ++p) {
+    const int32_t c0 = S.child0[p], c1 = S.child1[p];
+    if (c0 < 0 || c1 < 0 || S.child0[c0] < 0 || S.child1[c0] < 0 || S.child0[c1] < 0 || S.child1[c1] < 0) continue;
+    const std::array<int32_t, 4> g = {S.child0[c0], S.child1[c0], S.child0[c1], S.child1[c1]};
+    for (int32_t t : g) done[t] = 1;
+    groups.push_back(g);
+  }
+  for (int32_t t = 0; t < nc;) {
+    if (done[t]) {
+      ++t;
+      continue;
+    }
+    std::array<int32_t, 4> g = {-1, -1, -1, -1};
+    for (int i = 0; i < 4 && t < nc && !done[t]; ++i, ++t) g[i] = t;
+    groups.push_back(g);
+  }
+  std::sort(groups.begin(), groups.end(),
+            [](const std::array<int32_t, 4>& a, const std::array<int32_t, 4>& b) { return a[0] < b[0]; });
+  std::vector<std::vector<int32_t>> ge(groups.size());
+  std::vector<double> work(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const auto& g = groups[gi];
+    int64_t pos[4], end[4];
+    for (int i = 0; i < 4; ++i) {
+      pos[i] = g[i] >= 0 ? S.adm_ptr[g[i]] : 0;
+      end[i] = g[i] >= 0 ? S.adm_ptr[g[i] + 1] : 0;
+    }
+    auto key = [&](int32_t c) { return std::make_pair(S.cbegin[c], c); };
+    std::vector<int32_t>& out = ge[gi];
+    double blocks = 0.0;
+    for (;;) {  // merge the four lists (each ordered by position of the column cluster)
+      int32_t sig = -1;
+      for (int i = 0; i < 4; ++i)
+        if (pos[i] < end[i] && (sig < 0 || key(S.adm_col[pos[i]]) < key(sig))) sig = S.adm_col[pos[i]];
+      if (sig < 0) break;
+      int32_t en[8] = {sig, -1, -1, -1, -1, 0, 0, 0};
+      for (int i = 0; i < 4; ++i)
+        if (pos[i] < end[i] && S.adm_col[pos[i]] == sig) {
+          en[1 + i] = static_cast<int32_t>(pos[i]++);
+          blocks += 1.0;
+        }
+      out.insert(out.end(), en, en + 8);
+    }
+    work[gi] = 1.0 + blocks;
+  }
+  double total = 0.0;
+  for (double w : work) total += w;
+  const int64_t ng = static_cast<int64_t>(groups.size());
+  std::vector<int64_t> cut(9, ng);
+  cut[0] = 0;
+  double acc = 0.0;
+  int x = 1;
+  for (int64_t gi = 0; gi < ng && x < 8; ++gi) {
+    acc += work[gi];
+    if (acc >= total * x / 8.0) cut[x++] = gi + 1;
+  }
+  int64_t L = 1;
+  for (int c = 0; c < 8; ++c) L = std::max<int64_t>(L, cut[c + 1] - cut[c]);
+  std::vector<int32_t> rows(8 * L * 4, -1), ents;
+  std::vector<int64_t> ptr(8 * L + 1, 0);
+  for (int c = 0; c < 8; ++c)
+    for (int64_t q = 0; q < L; ++q) {
+      const int64_t slot = c * L + q, gi = cut[c] + q;
+      if (gi < cut[c + 1]) {
+        for (int i = 0; i < 4; ++i) rows[4 * slot + i] = groups[gi][i];
+        ents.insert(ents.end(), ge[gi].begin(), ge[gi].end());
+      }
+      ptr[slot + 1] = static_cast<int64_t>(ents.size() / 8);
+    }
+  H.mgrp_rows.upload(rows);
+  H.mgrp_ptr.upload(ptr);
+  H.mgrp_tasks.upload(ents);
+  H.mgrp_n = 8 * L;
+}
+
 }  // namespace
 
 // the row order of the coupling kernels (built on first use, rebuilt when the
 // row-order knob changes): XCD chunks of equal admissible-block count, or
-// interleaved
+// interleaved; schedule 3 also builds the row groups of mcoupling_grp (passes of
+// other widths use the XCD chunks)
 void ensure_row_order(h2_handle_s& H) {
-  const int kind = H.tune_order == 2 ? 2 : 1;
+  const int kind = H.tune_order == 2 || H.tune_order == 3 ? H.tune_order : 1;
   if (H.morder.p == nullptr || H.morder_kind != kind) {
     const std::vector<int32_t> ord = kind == 2 ? interleaved_rows(H.S) : balanced_rows(H.S);
     H.morder.upload(ord);
     H.morder_items = static_cast<int64_t>(ord.size());
+    if (kind == 3 && H.mgrp_n == 0) build_groups(H);
     H.morder_kind = kind;
   }
 }
@@ -1137,6 +1449,10 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
         break;
       default: throw Error(H2_EINVAL, "on-the-fly coupling supports real kernels only");
     }
+  } else if (NT == 2 && H.morder_kind == 3) {
+    mcoupling_grp<<<static_cast<unsigned>(H.mgrp_n), 256, 0, st>>>(
+        H.mgrp_n, H.mgrp_rows.as<int32_t>(), H.mgrp_ptr.as<int64_t>(), H.mgrp_tasks.as<int32_t>(), H.Smat.as<float>(),
+        xh, yh);
   } else {
     mcoupling<NT><<<gco, 256, 0, st>>>(nit, ord, H.adm_ptr.as<int64_t>(), H.adm_col.as<int32_t>(),
                                        H.Smat.as<float>(), xh, yh);
@@ -1161,10 +1477,14 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     e3 = prof_event(H);
     H2_HIP(hipEventRecord(e3, st));
   }
-  mnear_backward16<2 * NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
-                                                H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
-                                                H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
-                                                H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
+  if (H.near_row64)
+    mnear_stream16<2 * NT><<<grid8(nl), 256, 0, st>>>(nl, H.near_rows.as<NearRow>(), H.near_blocks.as<NearBlock>(),
+                                                      H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
+  else
+    mnear_backward16<2 * NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                        H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                                        H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
+                                                        H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
   mpermute_out<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
   H2_HIP(hipGetLastError());
   if (H.prof) {
@@ -1279,7 +1599,7 @@ bool matvec_multi_ready(const h2_handle_s& H, int nrhs, int dtype) {
   const int rp = pass_columns(H, nrhs, dtype);
   const size_t need_v = static_cast<size_t>(H.S.n) * rp * 4, need_h = static_cast<size_t>(H.S.nclusters) * 64 * rp * 4;
   return H.mxc.bytes >= need_v && H.mxhat.bytes >= need_h && H.morder.p != nullptr &&
-         H.morder_kind == (H.tune_order == 2 ? 2 : 1);
+         H.morder_kind == (H.tune_order == 2 || H.tune_order == 3 ? H.tune_order : 1);
 }
 
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,

@@ -36,7 +36,10 @@ int& knob_ref(h2_handle_s& H, int knob) {
 std::vector<int> knob_values(const h2_handle_s& H, int knob, int nrhs, int dtype) {
   const bool cx = dtype == H2_C128 || dtype == H2_C64;
   if (knob == H2_TUNE_PASS_COLUMNS && !cx && nrhs >= 2 && matvec_multi_supported(H)) return {32, 64};
-  if (knob == H2_TUNE_ROW_ORDER && nrhs >= 2 && matvec_multi_supported(H)) return {1, 2};
+  if (knob == H2_TUNE_ROW_ORDER && nrhs >= 2 && matvec_multi_supported(H)) {
+    if (!cx && !H.is_complex && !H.otf) return {1, 2, 3};
+    return {1, 2};
+  }
   if (knob == H2_TUNE_SMALL_SLOT && applicable_knob(H, nrhs, dtype) == H2_TUNE_SMALL_SLOT) return {16, 32};
   return {};
 }
@@ -64,7 +67,7 @@ void set_tuning(h2_handle_s& H, int knob, int value) {
     if (value == 16 && H.S.k > 16) throw Error(H2_EINVAL, "slots of 16 lanes need k <= 16");
     H.tune_slot = value;
   } else if (knob == H2_TUNE_ROW_ORDER) {
-    if (value != 0 && value != 1 && value != 2) throw Error(H2_EINVAL, "H2_TUNE_ROW_ORDER takes 0, 1 or 2");
+    if (value < 0 || value > 3) throw Error(H2_EINVAL, "H2_TUNE_ROW_ORDER takes 0, 1, 2 or 3");
     H.tune_order = value;
     // a row order already in use is rebuilt now, not in a later product
     if (H.morder.p != nullptr) ensure_row_order(H);

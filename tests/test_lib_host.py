@@ -156,10 +156,10 @@ def test_tuning_argument_errors():
         h2.h2_set_tuning(h, "pass_columns", 64)
         h2.h2_set_tuning(h, "pass_columns", 0)
         h2.h2_set_tuning(h, "small_slot", 32)
-        for v in (1, 2, 0):
+        for v in (1, 2, 3, 0):
             h2.h2_set_tuning(h, "row_order", v)
         for knob, value in (("pass_columns", 48), ("small_slot", 8), ("small_slot", 16), (7, 32), (-1, 0),
-                            ("row_order", 3), ("row_order", -1)):
+                            ("row_order", 4), ("row_order", -1)):
             with pytest.raises(h2.H2Error) as e:
                 h2.h2_set_tuning(h, knob, value)
             assert e.value.code == h2.H2_EINVAL
