@@ -310,14 +310,17 @@ int h2_recompress(h2_handle h, double eps, int max_rank, h2_recompress_info* inf
  *                         blocks of a row cluster at a time, needs k <= 16) or 32
  *                         (two).  Built-in rule: 16 if k <= 16, else 32.
  *   H2_TUNE_ROW_ORDER     many right-hand sides on the matrix-core path (real
- *                         or complex): the order in which the workgroups of the
- *                         coupling kernels take the row clusters, 1 (eight
- *                         contiguous ranges of equal work, one per XCD: rows
- *                         that share column clusters share an L2) or 2 (natural
- *                         order, four rows per workgroup, workgroups dealt
- *                         round-robin to the XCDs: neighbouring rows run at the
- *                         same time on every XCD).  Built-in rule: 1.  Only
- *                         h2_tune_knob tunes it.
+ *                         or complex): how the workgroups of the coupling
+ *                         kernels take the row clusters, 1 (one row per wave,
+ *                         eight contiguous ranges of equal work, one per XCD:
+ *                         rows that share column clusters share an L2), 2
+ *                         (natural order, four rows per workgroup, workgroups
+ *                         dealt round-robin to the XCDs) or 3 (real stored S,
+ *                         64-column passes: four neighbouring row clusters per
+ *                         workgroup, each x^_sigma they share staged once in LDS
+ *                         for all four; the same sums in the same order as 1;
+ *                         other passes take 1).  Built-in rule: 3 for real
+ *                         stored S, else 1.  Only h2_tune_knob tunes it.
  * h2_tune runs the product the way h2_matvec(h, nrhs, dtype, ...) would, with
  * every value of the knob that path has: one untimed and `reps` timed products
  * each on library-owned vectors (allocated for the call), timed with HIP events

@@ -126,7 +126,7 @@ struct h2_handle_s {
   int tune_pass = 0;  // right-hand sides per many-RHS pass: 32 or 64
   int tune_slot = 0;  // lanes per block-row slot of the small-k coupling: 16 or 32
   int tune_order = 0; // schedule of the many-RHS coupling: 1 XCD chunks, 2 interleaved,
-                      // 3 row groups sharing x^ (0: rule, 1)
+                      // 3 row groups sharing x^ (0: rule, 3 for real stored S, else 1)
   int morder_kind = 0;  // the schedule morder (and the groups) hold
   // schedule 3: row groups (4 cluster ids each, -1 unused), their entry ranges and
   // entries (column cluster, the block of each of the 4 rows or -1, 3 x padding)

@@ -145,12 +145,14 @@ __device__ inline void store_hat(float* __restrict__ out, const f32x16 (&acc)[2]
 }
 
 // the output block of wave `g` when row blocks are dealt to the XCDs in
-// contiguous chunks (workgroups are dispatched round-robin over 8 XCDs)
+// contiguous chunks (workgroups are dispatched round-robin over 8 XCDs).  The
+// value is wave-uniform and is returned as such (readfirstlane), so everything
+// derived from it stays in scalar registers.  Item counts stay below 2^31.
 __device__ inline int64_t xcd_item(int64_t items) {
   const int64_t nwg = gridDim.x;
   const int64_t per = (nwg + 7) / 8;
   const int64_t wg = static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
-  return wg * 4 + threadIdx.x / 64;  // 4 waves per workgroup, one item each
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(wg * 4 + threadIdx.x / 64));  // 4 waves per workgroup
 }
 
 // ---------------------------------------------------------------- permutations
@@ -861,7 +863,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
     int nleaves, const NearRow* __restrict__ rows, const NearBlock* __restrict__ blocks, const float* __restrict__ N,
     const float* __restrict__ Vb, const float* __restrict__ xc, const float* __restrict__ yhat,
     float* __restrict__ yc) {
-  const int64_t it = xcd_item(nleaves);
+  // one leaf per wave: its index is wave-uniform, so the row, the block
+  // descriptors and the step iterator live in scalar registers
+  const int it = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_item(nleaves)));
   if (it >= nleaves) return;
   const NearRow d = rows[it];
   switch ((d.r + 15) >> 4) {  // wave-uniform: one leaf per wave
@@ -1370,9 +1374,15 @@ void build_groups(h2_handle_s& H) {
 // the row order of the coupling kernels (built on first use, rebuilt when the
 // row-order knob changes): XCD chunks of equal admissible-block count, or
 // interleaved; schedule 3 also builds the row groups of mcoupling_grp (passes of
-// other widths use the XCD chunks)
+// other widths use the XCD chunks).  Unset, the knob means 3 for real stored
+// coupling matrices and 1 otherwise.
+int row_schedule(const h2_handle_s& H) {
+  if (H.tune_order != 0) return H.tune_order;
+  return !H.is_complex && !H.otf ? 3 : 1;  // built-in rule: row groups wherever they apply
+}
+
 void ensure_row_order(h2_handle_s& H) {
-  const int kind = H.tune_order == 2 || H.tune_order == 3 ? H.tune_order : 1;
+  const int kind = row_schedule(H);
   if (H.morder.p == nullptr || H.morder_kind != kind) {
     const std::vector<int32_t> ord = kind == 2 ? interleaved_rows(H.S) : balanced_rows(H.S);
     H.morder.upload(ord);
@@ -1599,7 +1609,7 @@ bool matvec_multi_ready(const h2_handle_s& H, int nrhs, int dtype) {
   const int rp = pass_columns(H, nrhs, dtype);
   const size_t need_v = static_cast<size_t>(H.S.n) * rp * 4, need_h = static_cast<size_t>(H.S.nclusters) * 64 * rp * 4;
   return H.mxc.bytes >= need_v && H.mxhat.bytes >= need_h && H.morder.p != nullptr &&
-         H.morder_kind == (H.tune_order == 2 || H.tune_order == 3 ? H.tune_order : 1);
+         H.morder_kind == row_schedule(H);
 }
 
 void matvec_multi(h2_handle_s& H, int nrhs, int dtype, const void* x, int64_t ldx, void* y, int64_t ldy,
