@@ -259,18 +259,19 @@ def copy_probe(torch, gib=2.0, reps=5):
     return {"bytes_per_copy": 2 * 4 * n, "GBs": 2 * 4 * n * reps / el / 1e9}
 
 
-def recorded_traffic(workload):
-    """HBM bytes per coupling launch from the committed PMC summary, or None if the
-    kernel source changed since the counters were taken (or none were taken)."""
+def recorded_traffic(workload, kernel="coupling64", source="matvec.hip"):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    profiles/<kernel>_<workload>_pmc.md, or None if the kernel's source file
+    changed since the counters were taken (or none were taken)."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", "coupling64_%s_pmc.md" % workload)
-    src = os.path.join(ROOT, "paper_2203_05665_amd", "csrc", "matvec.hip")
+    prof = os.path.join(ROOT, "profiles", "%s_%s_pmc.md" % (kernel, workload))
+    src = os.path.join(ROOT, "paper_2203_05665_amd", "csrc", source)
     if not os.path.exists(prof):
         return None
     text = open(prof).read()
-    mt = re.search(r"traffic_bytes_per_launch coupling64: (\d+)", text)
-    mh = re.search(r"matvec.hip sha256 prefix: ([0-9a-f]+)", text)
+    mt = re.search(r"traffic_bytes_per_launch %s: (\d+)" % re.escape(kernel), text)
+    mh = re.search(r"%s sha256 prefix: ([0-9a-f]+)" % re.escape(source), text)
     if not (mt and mh):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != mh.group(1):
@@ -390,6 +391,8 @@ def run_multi(args, workload, full=True):
     X = torch.tensor(I.random_vector(n, seed, "normal", nrhs=R), dtype=torch.float64, device="cuda")
     X = X.t().contiguous().t()
     Y = torch.zeros_like(X)
+    if getattr(args, "copy_probe", False):
+        copy = copy_probe(torch)  # a copy of known size, for the counter calibration
     tuning = A.tune(R, "f64", reps=5)  # tile shapes for R columns, before the timed region
     tuning_order = A.tune(R, "f64", reps=5, knob="row_order")
     log("bench: tuning %s %s" % (tuning, tuning_order))
@@ -400,6 +403,8 @@ def run_multi(args, workload, full=True):
     except Exception as e:  # reported, not fatal
         graph = {"error": repr(e)}
     k = info["k"]
+    # the coupling kernel the tuned schedule runs (row groups on 64-column passes)
+    coup_kernel = "mcoupling_grp" if tuning_order.get("chosen") == 3 and tuning.get("chosen") == 64 else "mcoupling"
     # every step as a dense contraction over R columns: V twice, E twice (dense on
     # this path), S, near field
     flops_total = 2.0 * R * (2.0 * n * k + 2.0 * k * k * (info["nclusters"] - 1) + k * k * info["n_adm"]
@@ -414,13 +419,16 @@ def run_multi(args, workload, full=True):
         "config": {"workload": workload, "mesh": "%s level %d" % (kind, level), "triangles": n,
                    "order_m": order, "k": k, "leaf": leaf, "eta": 0.5, "storage": storage, "rhs": R},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_F32_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": achieved / MFMA_F32_PEAK_TFS, "traffic": None, "kernel": "mcoupling",
+                     "frac": achieved / MFMA_F32_PEAK_TFS,
+                     "traffic": recorded_traffic(workload, coup_kernel, "matvec_multi.hip"), "kernel": coup_kernel,
                      "algorithmic_flops_per_launch": coup_flops, "avg_launch_ms": coup_ms},
         "path": {"flops": flops_total, "TFLOPs": flops_total / (el / args.steps) / 1e12,
                  "phase_ms": {kk: v[0] / max(1, v[1]) for kk, v in prof.items()}, "build_s": build_s,
                  "device_bytes": info["bytes_total"]},
         "tuning": tuning, "tuning_row_order": tuning_order, "graph_replay": graph,
     }
+    if getattr(args, "copy_probe", False):
+        out["copy_probe"] = copy
     A.close()
     del A
     torch.cuda.empty_cache()

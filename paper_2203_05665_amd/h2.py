@@ -391,7 +391,7 @@ def h2_tune(h, nrhs=1, dtype="f64", reps=10, stream=None, knob=None) -> dict:
 
 
 def h2_set_tuning(h, knob, value):
-    """Set a tile knob ("pass_columns" or "small_slot") directly; 0 restores the rule."""
+    """Set a tile knob ("pass_columns", "small_slot" or "row_order") directly; 0 restores the rule."""
     _check(lib().h2_set_tuning(h, TUNE_KNOBS[knob] if isinstance(knob, str) else int(knob), int(value)))
 
 
