@@ -341,3 +341,36 @@ def test_symmetric_storage_edge_cases(case, otf):
         assert rel(gpu_matvec(A, x), H.matvec(x)) <= 1e-12
     finally:
         A.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_near_field_fallback_kernels(storage):
+    """The kernels kept for structures outside the fast paths' limits.  Leaves of
+    up to 87 triangles (leaf size 100, m = 3) take the per-block near field
+    (near_backward) for one vector; a row with 67 near blocks (5,120 triangles,
+    leaf size 8, m = 4) takes the per-block many-column near field
+    (mnear_backward16) for 40 columns, while the single vector still runs
+    near_backward64 (at most 256 blocks per row)."""
+    for kind, level, m, leaf in (("sphere", 3, 3, 100), ("sphere", 4, 4, 8)):
+        H = oracle(kind, level, m, leaf)
+        n = H.mesh.n
+        x = I.random_vector(n, 5, "normal")
+        ref, ref_abs = H.matvec(x), H.matvec(np.abs(x))
+        A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage=storage)
+        try:
+            y = gpu_matvec(A, x)
+            assert err(storage, y, ref, ref_abs) <= TOL[storage], (kind, level, leaf)
+            if storage == "f32":
+                bounds.check(y, ref, ref_abs, storage, "fallback %s%d leaf %d" % (kind, level, leaf))
+            if m == 4 and storage == "f32":
+                X = np.random.default_rng(9).standard_normal((n, 40))
+                xd = torch.tensor(np.ascontiguousarray(X.T), device="cuda").t()
+                yd = torch.zeros_like(xd)
+                A.matvec(xd, yd)
+                torch.cuda.synchronize()
+                Y = yd.cpu().numpy()
+                for j in (0, 39):
+                    bounds.check(Y[:, j], H.matvec(X[:, j]), H.matvec(np.abs(X[:, j])), storage,
+                                 "fallback multi %s%d leaf %d col %d" % (kind, level, leaf, j))
+        finally:
+            A.close()
