@@ -15,13 +15,17 @@ wave number) with 1..R right-hand sides.  The engine
   matrix, restarted GMRES for Helmholtz, FP64 iterative refinement for FP32
   storage), whose vector algebra, inner products and small solves all run in
   the library's kernels;
-* on every scheduler tick asks each request which product it needs, groups the
-  requests by structure and by product flags (outer residuals of a refinement
-  accumulate in FP64), lets each solver write its operand into the structure's
-  product buffer, and issues ONE many-right-hand-side product per group (in
-  chunks of at most `product_width` columns) on that structure's stream, so
-  requests on different meshes overlap on the device and requests on the same
-  mesh share one pass over its matrix data;
+* steps every resident structure on its own stream and at its own pace: when
+  the structure's previous step has completed on the device (an event, polled
+  without blocking), it retires its finished requests, asks each remaining one
+  which product it needs, groups them by product flags (outer residuals of a
+  refinement accumulate in FP64), lets each solver write its operand into the
+  structure's product buffer, and issues ONE many-right-hand-side product per
+  group (in chunks of at most `product_width` columns), then the solvers' update
+  steps, and records a new event.  Requests on different meshes overlap on the
+  device without waiting for each other's steps (a small mesh iterates while a
+  large one computes), and requests on the same mesh share one pass over its
+  matrix data;
 * reports per-request latency (arrival to result), p50/p99 and throughput.
 
 A backend object supplies the structures, the products and the solvers, so the
@@ -119,6 +123,12 @@ class GPUBackend:
     def new_stream(self):
         return self.torch.cuda.Stream(device=self.device)
 
+    def mark(self, stream):
+        """An event recorded on `stream` now (the end of the work issued so far)."""
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return ev
+
     def refine(self):
         return self.storage != "f64"
 
@@ -208,6 +218,7 @@ class _Resident:
     stream: object
     active: int = 0
     last_used: float = 0.0
+    pending: object = None         # event at the end of the structure's last issued step
 
 
 class _Arena:
@@ -272,7 +283,9 @@ class H2Server:
         self._est: Dict[tuple, int] = {}
         self.ticks = 0
         self.batched_products = 0
-        self.busy_s = 0.0          # wall time of ticks that issued products (device work and host steps)
+        self.busy_s = 0.0          # wall time with at least one request active (solving or waiting on the device)
+        self.host_s = 0.0          # wall time of ticks that issued steps (host side of the scheduler)
+        self._t_last = None        # clock of the previous tick, while requests were active
 
     # -- registry ---------------------------------------------------------------------
     def register_mesh(self, name: str, vertices, triangles):
@@ -382,6 +395,7 @@ class H2Server:
                     if res.stream is not None:                # the right-hand sides came from the default stream
                         res.stream.wait_stream(self.be.torch.cuda.default_stream(res.stream.device))
                     q._solver.begin(q.b, None, self._sid(res.stream))
+                self._mark(res)                               # its status is read after this completes
             except Exception as e:
                 self.arena.free(ws)
                 self.free_slots.append(slot)
@@ -402,22 +416,44 @@ class H2Server:
             return _nullcontext()
         return self.be.torch.cuda.stream(stream)
 
+    def _mark(self, res):
+        if res.stream is not None:
+            res.pending = self.be.mark(res.stream)
+
+    @staticmethod
+    def _ready(res):
+        """Whether the structure's last issued step has completed on the device."""
+        return res.pending is None or res.pending.query()
+
     def tick(self) -> int:
-        """Admit arrivals, issue one product per (structure, flags) group and chunk,
-        advance every active request.  Returns the number of products."""
+        """Admit arrivals; for every structure whose last step has completed,
+        retire its finished requests and issue its next step (one product per
+        flags group and chunk, then every request's update).  Returns the number
+        of products issued; waits briefly when no structure is ready."""
         now = self.clock()
+        t_start = time.perf_counter()
+        if self._t_last is not None:
+            self.busy_s += t_start - self._t_last
         self._admit(now)
+        self._t_last = t_start if self.active else None
         if not self.active:
             return 0
-        t_start = time.perf_counter()
         by_key: Dict[tuple, List[Request]] = {}
         for q in self.active:
             by_key.setdefault(q.key, []).append(q)
         width = getattr(self.be, "product_width", self.max_rhs)
         nprod = 0
+        stepped = False
+        n_before = len(self.active)
         for key, reqs in by_key.items():
             res = self.resident[key]
+            if not self._ready(res):
+                continue
+            stepped = True
             res.last_used = now
+            reqs = self._retire(res, reqs)
+            if not reqs:
+                continue
             sid = self._sid(res.stream)
             X, Y = self.be.buffers(res.obj)
             classes: Dict[int, List[Request]] = {}
@@ -438,21 +474,26 @@ class H2Server:
                             q._solver.advance(Y[:, off:off + q.nrhs], sid)
                             off += q.nrhs
                         nprod += 1
+            self._mark(res)
+        if not stepped:                                       # every structure is busy on the device
+            time.sleep(1e-4)
+            return nprod
+        if len(self.active) < n_before:                       # requests finished: their room is free now
+            self._admit(self.clock())
         self.batched_products += nprod
-        self._sync()
-        self._retire()
         self.ticks += 1
-        self.busy_s += time.perf_counter() - t_start
+        self.host_s += time.perf_counter() - t_start
         return nprod
 
     def _sync(self):
         if self.be.device.type == "cuda":
             self.be.torch.cuda.synchronize()
 
-    def _retire(self):
-        now = None
+    def _retire(self, res, reqs):
+        """Finish the requests of `res` whose solver has stopped (the structure's
+        last step has completed, so their status is current); returns the others."""
         keep, done = [], []
-        for q in self.active:
+        for q in reqs:
             st = q._solver.poll()
             q.iterations, q.products = st["iterations"], st["products"]
             if st["state"] == "product":
@@ -462,18 +503,20 @@ class H2Server:
             q.status = st["state"]
             if q.status == "failed":
                 q.error = "%s (%d right-hand sides)" % (st["message"], q.nrhs)
-            res = self.resident[q.key]
             with self._on(res.stream):
                 q._solver.solution(q.result, self._sid(res.stream))
             done.append(q)
         if done:
-            self._sync()
+            if res.stream is not None:
+                res.stream.synchronize()                      # the solutions are copied before release
             now = self.clock()
-        for q in done:
-            q.finish = now
-            self._release(q)
-            self.finished.append(q)
-        self.active = keep
+            for q in done:
+                q.finish = now
+                self._release(q)
+                self.finished.append(q)
+            gone = set(id(q) for q in done)
+            self.active = [q for q in self.active if id(q) not in gone]
+        return keep
 
     def _release(self, q):
         q._solver.close()
@@ -532,6 +575,7 @@ class H2Server:
             "rhs_solved": int(sum(q.nrhs for q in done)),
             "ticks": self.ticks, "batched_products": self.batched_products,
             "busy_s": self.busy_s, "busy_frac": self.busy_s / span if span > 0 else None,
+            "host_s": self.host_s,
             "errors": dict(Counter(q.error for q in self.finished if q.status in ("failed", "cancelled"))),
         }
 
