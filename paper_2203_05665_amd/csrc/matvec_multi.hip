@@ -289,13 +289,18 @@ __device__ inline void mma_tile_k64(const float* __restrict__ As, const float* _
     for (int e = 0; e < 4; ++e) acc = mfma(a[p][e], b[p][e], acc);
 }
 
-__global__ __launch_bounds__(256) void mcoupling_grp(int64_t ngroups, const int32_t* __restrict__ grows,
-                                                     const int64_t* __restrict__ gent,
-                                                     const int32_t* __restrict__ ents, const float* __restrict__ S,
-                                                     const float* __restrict__ xhat, float* __restrict__ yhat) {
+// LDS holds one S block and one x^_sigma (34 KB) and a lane at most 128
+// registers, so four workgroups share a CU: while one waits at its barriers or
+// for its staged loads, the others multiply.  Per task the next operands are
+// loaded into registers before the multiplies and written to LDS between two
+// barriers after them.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mcoupling_grp(
+    int64_t ngroups, const int32_t* __restrict__ grows, const int64_t* __restrict__ gent,
+    const int32_t* __restrict__ ents, const float* __restrict__ S, const float* __restrict__ xhat,
+    float* __restrict__ yhat) {
   constexpr int RP = 64;
-  __shared__ __align__(16) float sbuf[2][64 * kGrpPitch];
-  __shared__ __align__(16) float xbuf[2][64 * kGrpPitch];
+  __shared__ __align__(16) float sbuf[64 * kGrpPitch];
+  __shared__ __align__(16) float xbuf[64 * kGrpPitch];
   const int64_t per = gridDim.x / 8;  // groups per XCD chunk (the grid is 8 chunks)
   const int64_t g = static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (g >= ngroups) return;  // whole workgroup
@@ -329,11 +334,10 @@ __global__ __launch_bounds__(256) void mcoupling_grp(int64_t ngroups, const int3
   if (e0 < e1) {
     fetch(S + static_cast<int64_t>(first_block(e0)) * 4096, sreg);
     fetch(xhat + static_cast<int64_t>(ents[8 * e0]) * RP * 64, xreg);
-    put(sbuf[0], sreg);
-    put(xbuf[0], xreg);
+    put(sbuf, sreg);
+    put(xbuf, xreg);
   }
   __syncthreads();
-  int sc = 0, xcur = 0;
   for (int64_t e = e0; e < e1; ++e) {
     const int32_t* en = ents + 8 * e;
     const int32_t blk[4] = {en[1], en[2], en[3], en[4]};
@@ -349,13 +353,11 @@ __global__ __launch_bounds__(256) void mcoupling_grp(int64_t ngroups, const int3
         if (newx) nb = first_block(e + 1);
         if (nb >= 0) fetch(S + static_cast<int64_t>(nb) * 4096, sreg);
         if (newx) fetch(xhat + static_cast<int64_t>(ents[8 * e + 8]) * RP * 64, xreg);
-        mma_tile_k64(sbuf[sc] + (32 * ti + r) * kGrpPitch + 4 * h, xbuf[xcur] + (32 * tj + r) * kGrpPitch + 4 * h,
-                     acc[i]);
-        if (nb >= 0) put(sbuf[sc ^ 1], sreg);
-        if (newx) put(xbuf[xcur ^ 1], xreg);
+        mma_tile_k64(sbuf + (32 * ti + r) * kGrpPitch + 4 * h, xbuf + (32 * tj + r) * kGrpPitch + 4 * h, acc[i]);
+        __syncthreads();  // every wave is done with this task's operands
+        if (nb >= 0) put(sbuf, sreg);
+        if (newx) put(xbuf, xreg);
         __syncthreads();
-        sc ^= 1;
-        if (newx) xcur ^= 1;
       }
     }
   }
