@@ -290,7 +290,7 @@ def otf_roofline(info, coup_avg_ms, storage):
             "entries_per_launch": entries, "avg_launch_ms": coup_avg_ms}
 
 
-def variant_roofline(info, ph, storage, kw):
+def variant_roofline(info, ph, storage, kw, leaf=64):
     """Roofline of the dominant kernel of a variant: the on-the-fly coupling
     (ALU) when it is the longest phase, else the phase that streams stored data
     from HBM (symmetric coupling: the kept S blocks; near field: the kept panels
@@ -303,7 +303,8 @@ def variant_roofline(info, ph, storage, kw):
         ms = ph["coupling"]
     else:
         nbytes = float(info["near_entries_stored"] + info["n"] * info["k"]) * sb
-        kern, ms = ("near_backward_sym" if kw.get("symmetric") else "near_backward"), ph["near"]
+        kern = "near_backward_sym" if kw.get("symmetric") else ("near_backward64" if leaf <= 64 else "near_backward")
+        ms = ph["near"]
     ach = nbytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": None, "kernel": kern, "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": ms}
@@ -674,7 +675,7 @@ def main():
             out["variants"][vname] = {"value": args.steps / elb, "unit": "matvec/s", "ms_per_step": 1e3 * elb / args.steps,
                                       "device_bytes": B.info["bytes_total"],
                                       "algorithmic_bytes": B.info["matvec_bytes"], "phase_ms": ph,
-                                      "roofline": variant_roofline(B.info, ph, storage, kw)}
+                                      "roofline": variant_roofline(B.info, ph, storage, kw, leaf)}
             B.close()
             del B
             torch.cuda.empty_cache()
@@ -701,7 +702,8 @@ def main():
             kern = "coupling_small" if inf["k"] <= 32 else "coupling_any"
             nbytes, ms = float(inf["s_blocks_stored"]) * inf["k"] ** 2 * sb, ph["coupling"]
         else:
-            kern = "near_backward_sym" if args.recompress_sym_near else "near_backward"
+            kern = "near_backward_sym" if args.recompress_sym_near else (
+                "near_backward64" if leaf <= 64 else "near_backward")
             nbytes, ms = float(inf["near_entries_stored"] + inf["n"] * inf["k"]) * sb, ph["near"]
         ach = nbytes / (ms * 1e-3) / 1e9
         out.setdefault("variants", {})["recompressed"] = {

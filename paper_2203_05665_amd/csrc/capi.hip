@@ -131,6 +131,11 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
         H->val_bytes = P.storage == H2_F64 ? 8 : 4;
         H->s_bytes = P.storage == H2_F64 ? 8 : (P.storage == H2_F32 ? 4 : 2);
         H->perm.upload(S.perm);
+        {
+          std::vector<int32_t> ip(S.perm.size());
+          for (size_t p = 0; p < S.perm.size(); ++p) ip[S.perm[p]] = static_cast<int32_t>(p);
+          H->iperm.upload(ip);
+        }
         H->cbegin.upload(S.cbegin);
         H->cend.upload(S.cend);
         H->parent.upload(S.parent);
@@ -182,8 +187,8 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
         };
         H->up_top = top_levels(64, true);
         H->down_top = top_levels(64, false);
-        H->mup_top = top_levels(8, true);
-        H->mdown_top = top_levels(8, false);
+        H->mup_top = top_levels(4, true);
+        H->mdown_top = top_levels(4, false);
         H->up_ptr_dev.upload(H->up_ptr);
         H->level_ptr_dev.upload(S.level_ptr);
         if (S.sym_s) {

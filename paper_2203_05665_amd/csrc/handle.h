@@ -87,6 +87,7 @@ struct h2_handle_s {
   // device structure
   h2::DBuf perm, cbegin, cend, parent, child0, child1, leaves, adm_ptr, adm_col, near_ptr, near_col,
       panel_off, up_list, pts;
+  h2::DBuf iperm;  // inverse of perm: the cluster-order position of every user index
   // near_backward64's descriptors (h2::NearRow per leaf, h2::NearBlock per near
   // block); near64: every leaf holds at most 64 triangles and every row at most 256
   // near blocks, so that kernel applies

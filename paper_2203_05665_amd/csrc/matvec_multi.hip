@@ -157,51 +157,78 @@ __device__ inline int64_t xcd_item(int64_t items) {
 
 // ---------------------------------------------------------------- permutations
 // User order (column-major, leading dimension ld) <-> cluster order
-// (position-major, RP columns), through an LDS tile of 64 positions x RP
-// columns per workgroup: the user-side gather/scatter runs along positions
-// (neighbouring positions are neighbouring triangles, so their indices are
-// close), the cluster-order side along columns (contiguous).  The tile's odd
-// row pitch keeps both LDS passes free of bank conflicts.
+// (position-major, RP columns), through an LDS tile of 64 user indices x RP
+// columns per workgroup, walked in user order: the user side reads or writes 64
+// consecutive indices of a column (one contiguous run per wave), the cluster side
+// one whole RP-column row per position, iperm[i] being the position of user
+// index i (a contiguous run of RP floats).  Both sides move whole cache lines,
+// so no line is fetched twice.  The tile's odd row pitch keeps both LDS passes
+// free of bank conflicts.  Columns rcur..RP-1 of the cluster-order rows are 0.
 template <typename XT, int RP>
-__global__ __launch_bounds__(256) void mpermute_in(int64_t n, int rcur, const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(256) void mpermute_in(int64_t n, int rcur, const int32_t* __restrict__ iperm,
                                                    const XT* __restrict__ x, int64_t ldx, float* __restrict__ xc) {
+  constexpr int PER = 64 * RP / 256;  // elements per thread and pass
   __shared__ float tile[64][RP + 1];
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
-  for (int idx = threadIdx.x; idx < 64 * RP; idx += 256) {
-    const int j = idx / 64, pl = idx % 64;
-    const int64_t p = p0 + pl;
-    float v = 0.f;
-    if (j < rcur && p < n) v = static_cast<float>(x[static_cast<int64_t>(j) * ldx + perm[p]]);
-    tile[pl][j] = v;
+  __shared__ int32_t pos[64];
+  const int t = threadIdx.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int32_t ip = iperm[min(i0 + t % 64, n - 1)];  // every wave loads the tile's positions
+  // all loads first (out-of-range elements read x[0] and are replaced by 0)
+  XT v[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int j = (t + 256 * s) / 64, il = t % 64;
+    const bool ok = j < rcur && i0 + il < n;
+    v[s] = x[ok ? static_cast<int64_t>(j) * ldx + i0 + il : 0];
+    v[s] = ok ? v[s] : XT(0);
   }
+  if (t < 64) pos[t] = i0 + t < n ? ip : 0;
+#pragma unroll
+  for (int s = 0; s < PER; ++s) tile[t % 64][(t + 256 * s) / 64] = static_cast<float>(v[s]);
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 64 * RP; idx += 256) {
-    const int pl = idx / RP, j = idx % RP;
-    const int64_t p = p0 + pl;
-    if (p < n) xc[p * RP + j] = tile[pl][j];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int il = (t + 256 * s) / RP, j = (t + 256 * s) % RP;
+    if (i0 + il < n) xc[static_cast<int64_t>(pos[il]) * RP + j] = tile[il][j];
   }
 }
 
 template <typename XT, int RP>
-__global__ __launch_bounds__(256) void mpermute_out(int64_t n, int rcur, const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(256) void mpermute_out(int64_t n, int rcur, const int32_t* __restrict__ iperm,
                                                     const float* __restrict__ yc, XT* __restrict__ y, int64_t ldy,
                                                     double alpha, bool ow) {
+  constexpr int PER = 64 * RP / 256;
   __shared__ float tile[64][RP + 1];
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
-  for (int idx = threadIdx.x; idx < 64 * RP; idx += 256) {
-    const int pl = idx / RP, j = idx % RP;
-    const int64_t p = p0 + pl;
-    tile[pl][j] = p < n ? yc[p * RP + j] : 0.f;
+  __shared__ int32_t pos[64];
+  const int t = threadIdx.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int32_t ip = iperm[min(i0 + t % 64, n - 1)];  // every wave loads the tile's positions
+  // the user-side operand of the update, loaded while the positions arrive
+  XT y0[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int j = (t + 256 * s) / 64, il = t % 64;
+    const bool ok = !ow && j < rcur && i0 + il < n;
+    y0[s] = y[ok ? static_cast<int64_t>(j) * ldy + i0 + il : 0];
+    y0[s] = ok ? y0[s] : XT(0);
   }
+  if (t < 64) pos[t] = i0 + t < n ? ip : 0;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 64 * RP; idx += 256) {
-    const int j = idx / 64, pl = idx % 64;
-    const int64_t p = p0 + pl;
-    if (j < rcur && p < n) {
-      XT* dst = y + static_cast<int64_t>(j) * ldy + perm[p];
-      const double y0 = ow ? 0.0 : static_cast<double>(*dst);
-      *dst = static_cast<XT>(y0 + alpha * static_cast<double>(tile[pl][j]));
-    }
+  float v[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int il = (t + 256 * s) / RP, j = (t + 256 * s) % RP;
+    v[s] = yc[static_cast<int64_t>(pos[il]) * RP + j];  // pos = 0 past n: a valid row
+  }
+#pragma unroll
+  for (int s = 0; s < PER; ++s) tile[(t + 256 * s) / RP][(t + 256 * s) % RP] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int j = (t + 256 * s) / 64, il = t % 64;
+    if (j < rcur && i0 + il < n)
+      y[static_cast<int64_t>(j) * ldy + i0 + il] =
+          static_cast<XT>(static_cast<double>(y0[s]) + alpha * static_cast<double>(tile[il][j]));
   }
 }
 
@@ -489,39 +516,94 @@ __global__ __launch_bounds__(256) void mtransfer_down(int first, int count, cons
 
 // Kronecker form of the two transfers (k = 64, interpolation bases):
 // E_c = E_x (x) E_y (x) E_z with E1[c][d][i][j] = l_j(xi_i) along axis d (i child
-// point, j parent polynomial), nu = nu_x + 4 nu_y + 16 nu_z.  One wave per output
-// cluster, lane = right-hand side: a lane holds the 64 coefficients of its column
-// in registers (one 256-byte row of x^, read as 16-byte vectors), so every axis
-// step is 16 register-local 4 x 4 products with the wave-uniform factor entries
-// (scalar loads) and no lane exchange.  A transfer reads 48 factor numbers
-// instead of a dense 64 x 64 E and takes 12 multiply-adds per coefficient
-// instead of 64: it is bound by the x^ / y^ rows it moves.  With 32 columns per
-// pass the upper half of the wave idles.
-// One axis step in place: v[nu] <- sum_i a(o, i) v[nu with digit d = i], o = the
-// digit d of nu; a(o, i) = E_d[i][o] (up, transposed) or E_d[o][i] (down).
-template <int D, bool TRANSPOSE>
-__device__ inline void kron_axis_regs(float (&v)[64], const float* __restrict__ e) {
-  constexpr int S = 1 << (2 * D);
+// point, j parent polynomial), nu = nu_x + 4 nu_y + 16 nu_z.  A transfer reads 48
+// factor numbers instead of a dense 64 x 64 E and takes 12 multiply-adds per
+// coefficient instead of 64: it is bound by the x^ / y^ tiles it moves.
+// One group of four waves per cluster.  The RP x 64 tile (RP columns of 64
+// coefficients) is moved between HBM and LDS with coalesced 16-byte accesses
+// (1 KB per wave instruction).  In LDS, lane j of wave w first takes the plane
+// nu_z = w of column j (16 coefficients, register-local x and y steps), then,
+// after a barrier, the coefficients with nu_y = w (the z step); every wave
+// writes back only what it read in that step, so three barriers order a
+// transfer.  The factor entries are wave-uniform scalar loads.
+constexpr int kTilePitch = 68;                   // LDS row pitch of a tile (floats)
+constexpr int kTileFloats = 64 * kTilePitch;     // one tile, up to 64 columns
+
+// a(o, i) = E_d[i][o] (up: transposed) or E_d[o][i] (down)
+template <bool TRANSPOSE>
+__device__ inline float kfac(const float* __restrict__ e, int o, int i) {
+  return e[TRANSPOSE ? 4 * i + o : 4 * o + i];
+}
+
+// x and y steps on one plane in place: v[q], q = nu_x + 4 nu_y
+template <bool TRANSPOSE>
+__device__ inline void kron_xy(float (&v)[16], const float* __restrict__ e) {
 #pragma unroll
-  for (int line = 0; line < 16; ++line) {
-    const int b = D == 0 ? 4 * line : D == 1 ? (line & 3) + 16 * (line >> 2) : line;
+  for (int line = 0; line < 4; ++line) {  // x: the four nu_x of one nu_y
     float t[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) t[i] = v[b + i * S];
+    for (int i = 0; i < 4; ++i) t[i] = v[4 * line + i];
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
       float r = 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) r += e[TRANSPOSE ? 4 * i + o : 4 * o + i] * t[i];
-      v[b + o * S] = r;
+      for (int i = 0; i < 4; ++i) r += kfac<TRANSPOSE>(e, o, i) * t[i];
+      v[4 * line + o] = r;
+    }
+  }
+#pragma unroll
+  for (int line = 0; line < 4; ++line) {  // y: the four nu_y of one nu_x
+    float t[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = v[line + 4 * i];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      float r = 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r += kfac<TRANSPOSE>(e + 16, o, i) * t[i];
+      v[line + 4 * o] = r;
     }
   }
 }
 
-__device__ inline void load_row64(const float* __restrict__ p, float (&v)[64]) {
+// z step of the coefficients with nu_y = w: out[o][x] = sum_z a_z(o, z) u[z][x]
+// with u[z][x] = tile[j][x + 4 w + 16 z]; ADD: out accumulates
+template <bool TRANSPOSE, bool ADD>
+__device__ inline void kron_z(const float* __restrict__ row, int w, const float* __restrict__ e, float (&out)[4][4]) {
+  float u[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const f4v t = ld4c(p + 4 * q);
+  for (int z = 0; z < 4; ++z) {
+    const f4v t = *reinterpret_cast<const f4v*>(row + 4 * w + 16 * z);
+    u[z][0] = t.x;
+    u[z][1] = t.y;
+    u[z][2] = t.z;
+    u[z][3] = t.w;
+  }
+#pragma unroll
+  for (int o = 0; o < 4; ++o)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      float r = 0.f;
+#pragma unroll
+      for (int z = 0; z < 4; ++z) r += kfac<TRANSPOSE>(e + 32, o, z) * u[z][x];
+      out[o][x] = ADD ? out[o][x] + r : r;
+    }
+}
+
+// tile (RP rows of 64 floats at src) -> LDS rows of pitch kTilePitch; g = thread of the group
+template <int RP>
+__device__ inline void tile_to_lds(const float* __restrict__ src, float* __restrict__ t, int g) {
+#pragma unroll
+  for (int s = 0; s < RP / 16; ++s) {
+    const int e = 4 * (g + 256 * s);
+    *reinterpret_cast<f4v*>(t + (e / 64) * kTilePitch + e % 64) = ld4c(src + e);
+  }
+}
+
+__device__ inline void plane_load(const float* __restrict__ row, int w, float (&v)[16]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f4v t = *reinterpret_cast<const f4v*>(row + 16 * w + 4 * q);
     v[4 * q] = t.x;
     v[4 * q + 1] = t.y;
     v[4 * q + 2] = t.z;
@@ -529,125 +611,164 @@ __device__ inline void load_row64(const float* __restrict__ p, float (&v)[64]) {
   }
 }
 
-// x^_c = E_c0^T x^_c0 + E_c1^T x^_c1 (lane j < RP: right-hand side j)
-template <int NT>
-__device__ inline void mup_kron(int32_t c, int j, const int32_t* __restrict__ child0,
-                                const int32_t* __restrict__ child1, const float* __restrict__ E1,
-                                float* __restrict__ xhat) {
-  constexpr int RP = 32 * NT;
-  float acc[64];
+__device__ inline void plane_store(float* __restrict__ row, int w, const float (&v)[16]) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int64_t ch = __builtin_amdgcn_readfirstlane(a == 0 ? child0[c] : child1[c]);
-    const float* e = E1 + ch * 48;
-    float v[64];
-    load_row64(xhat + (ch * RP + j) * 64, v);
-    kron_axis_regs<0, true>(v, e);
-    kron_axis_regs<1, true>(v, e + 16);
-    kron_axis_regs<2, true>(v, e + 32);
-#pragma unroll
-    for (int i = 0; i < 64; ++i) acc[i] = a == 0 ? v[i] : acc[i] + v[i];
-  }
-  float* out = xhat + (static_cast<int64_t>(c) * RP + j) * 64;
-#pragma unroll
-  for (int q = 0; q < 16; ++q)
-    *reinterpret_cast<f4v*>(out + 4 * q) = f4v{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+  for (int q = 0; q < 4; ++q)
+    *reinterpret_cast<f4v*>(row + 16 * w + 4 * q) = f4v{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
 }
 
-// y^_c += E_c y^_parent(c)
-template <int NT>
-__device__ inline void mdown_kron(int64_t c, int j, const int32_t* __restrict__ parent, const float* __restrict__ E1,
-                                  float* __restrict__ yhat) {
-  constexpr int RP = 32 * NT;
-  const int64_t p = __builtin_amdgcn_readfirstlane(parent[c]);
-  const float* e = E1 + c * 48;
-  float v[64];
-  load_row64(yhat + (p * RP + j) * 64, v);
-  kron_axis_regs<0, false>(v, e);
-  kron_axis_regs<1, false>(v, e + 16);
-  kron_axis_regs<2, false>(v, e + 32);
-  float* out = yhat + (c * RP + j) * 64;
+__device__ inline void zrow_store(float* __restrict__ row, int w, const float (&o)[4][4]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    f4v t = ld4c(out + 4 * q);
-    t.x += v[4 * q];
-    t.y += v[4 * q + 1];
-    t.z += v[4 * q + 2];
-    t.w += v[4 * q + 3];
-    *reinterpret_cast<f4v*>(out + 4 * q) = t;
+  for (int z = 0; z < 4; ++z) *reinterpret_cast<f4v*>(row + 4 * w + 16 * z) = f4v{o[z][0], o[z][1], o[z][2], o[z][3]};
+}
+
+// x^_c = E_c0^T x^_c0 + E_c1^T x^_c1 by the group of threads g = 0..255 with the LDS
+// tiles t (two); c < 0: the group only takes part in the barriers
+template <int NT>
+__device__ inline void kup_group(int64_t c, int g, const int32_t* __restrict__ child0, const int32_t* __restrict__ child1,
+                                 const float* __restrict__ E1, float* __restrict__ xhat, float* __restrict__ t) {
+  constexpr int RP = 32 * NT;
+  const int w = g / 64, j = g % 64;
+  int64_t ch[2] = {0, 0};
+  if (c >= 0) {
+    ch[0] = __builtin_amdgcn_readfirstlane(child0[c]);
+    ch[1] = __builtin_amdgcn_readfirstlane(child1[c]);
+    tile_to_lds<RP>(xhat + ch[0] * RP * 64, t, g);
+    tile_to_lds<RP>(xhat + ch[1] * RP * 64, t + kTileFloats, g);
+  }
+  __syncthreads();
+  if (c >= 0 && j < RP) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      float v[16];
+      float* row = t + a * kTileFloats + j * kTilePitch;
+      plane_load(row, w, v);
+      kron_xy<true>(v, E1 + ch[a] * 48);
+      plane_store(row, w, v);
+    }
+  }
+  __syncthreads();
+  if (c >= 0 && j < RP) {
+    float acc[4][4];
+    kron_z<true, false>(t + j * kTilePitch, w, E1 + ch[0] * 48, acc);
+    kron_z<true, true>(t + kTileFloats + j * kTilePitch, w, E1 + ch[1] * 48, acc);
+    zrow_store(t + j * kTilePitch, w, acc);
+  }
+  __syncthreads();
+  if (c >= 0) {
+    float* dst = xhat + c * RP * 64;
+#pragma unroll
+    for (int s = 0; s < RP / 16; ++s) {
+      const int e = 4 * (g + 256 * s);
+      *reinterpret_cast<f4v*>(dst + e) = *reinterpret_cast<const f4v*>(t + (e / 64) * kTilePitch + e % 64);
+    }
   }
 }
 
-// the parents of one level, one wave each
+// y^_c += E_c y^_parent(c), likewise (one LDS tile)
+template <int NT>
+__device__ inline void kdown_group(int64_t c, int g, const int32_t* __restrict__ parent, const float* __restrict__ E1,
+                                   float* __restrict__ yhat, float* __restrict__ t) {
+  constexpr int RP = 32 * NT;
+  const int w = g / 64, j = g % 64;
+  f4v own[RP / 16];
+  if (c >= 0) {
+    const int64_t p = __builtin_amdgcn_readfirstlane(parent[c]);
+#pragma unroll
+    for (int s = 0; s < RP / 16; ++s) own[s] = ld4c(yhat + c * RP * 64 + 4 * (g + 256 * s));
+    tile_to_lds<RP>(yhat + p * RP * 64, t, g);
+  }
+  __syncthreads();
+  if (c >= 0 && j < RP) {
+    float v[16];
+    float* row = t + j * kTilePitch;
+    plane_load(row, w, v);
+    kron_xy<false>(v, E1 + c * 48);
+    plane_store(row, w, v);
+  }
+  __syncthreads();
+  if (c >= 0 && j < RP) {
+    float out[4][4];
+    float* row = t + j * kTilePitch;
+    kron_z<false, false>(row, w, E1 + c * 48, out);
+    zrow_store(row, w, out);
+  }
+  __syncthreads();
+  if (c >= 0) {
+    float* dst = yhat + c * RP * 64;
+#pragma unroll
+    for (int s = 0; s < RP / 16; ++s) {
+      const int e = 4 * (g + 256 * s);
+      const f4v d = *reinterpret_cast<const f4v*>(t + (e / 64) * kTilePitch + e % 64);
+      *reinterpret_cast<f4v*>(dst + e) = own[s] + d;
+    }
+  }
+}
+
+// item of a per-cluster workgroup: the grid (a multiple of 8 workgroups) in eight
+// chunks of consecutive items, one per XCD, so siblings share an L2
+__device__ inline int64_t xcd_group_item() {
+  const int64_t per = gridDim.x / 8;
+  return static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+// the parents of one level, one workgroup each
 template <int NT>
 __global__ __launch_bounds__(256) void mtransfer_up_kron(int count, const int32_t* __restrict__ list,
                                                          const int32_t* __restrict__ child0,
                                                          const int32_t* __restrict__ child1,
                                                          const float* __restrict__ E1, float* __restrict__ xhat) {
-  const int it = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_item(count)));
-  if (it >= count) return;  // uniform per wave
-  constexpr int RP = 32 * NT;
-  const int j = threadIdx.x % 64;
-  if (j >= RP) return;
-  const int32_t c = __builtin_amdgcn_readfirstlane(list[it]);
-  float acc[64];
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int64_t ch = __builtin_amdgcn_readfirstlane(a == 0 ? child0[c] : child1[c]);
-    const float* e = E1 + ch * 48;
-    float v[64];
-    load_row64(xhat + (ch * RP + j) * 64, v);
-    kron_axis_regs<0, true>(v, e);
-    kron_axis_regs<1, true>(v, e + 16);
-    kron_axis_regs<2, true>(v, e + 32);
-#pragma unroll
-    for (int i = 0; i < 64; ++i) acc[i] = a == 0 ? v[i] : acc[i] + v[i];
-  }
-  float* out = xhat + (static_cast<int64_t>(c) * RP + j) * 64;
-#pragma unroll
-  for (int q = 0; q < 16; ++q)
-    *reinterpret_cast<f4v*>(out + 4 * q) = f4v{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+  __shared__ __attribute__((aligned(16))) float t[2 * kTileFloats];
+  const int64_t it = xcd_group_item();
+  if (it >= count) return;  // uniform per workgroup
+  kup_group<NT>(__builtin_amdgcn_readfirstlane(list[it]), threadIdx.x, child0, child1, E1, xhat, t);
 }
 
-// the clusters of one level, one wave each
+// the clusters of one level, one workgroup each
 template <int NT>
 __global__ __launch_bounds__(256) void mtransfer_down_kron(int first, int count, const int32_t* __restrict__ parent,
                                                            const float* __restrict__ E1, float* __restrict__ yhat) {
-  const int it = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_item(count)));
-  if (it >= count) return;  // uniform per wave
-  const int j = threadIdx.x % 64;
-  if (j >= 32 * NT) return;
-  mdown_kron<NT>(first + it, j, parent, E1, yhat);
+  __shared__ __attribute__((aligned(16))) float t[kTileFloats];
+  const int64_t it = xcd_group_item();
+  if (it >= count) return;
+  kdown_group<NT>(first + it, threadIdx.x, parent, E1, yhat, t);
 }
 
-// The top levels (few clusters each) in one workgroup of 8 waves, level by level
-// with a workgroup barrier between levels, as for one right-hand side.
-constexpr int kMTopWaves = 8;
+// The top levels (few clusters each) in one workgroup of kMTopGroups groups, level
+// by level; a level's clusters are taken kMTopGroups at a time, and the barriers
+// inside a transfer and after it also order the levels (a level reads the tiles
+// the previous one wrote).
+constexpr int kMTopGroups = 4;
 
 template <int NT>
-__global__ __launch_bounds__(64 * kMTopWaves) void mtransfer_up_kron_top(
+__global__ __launch_bounds__(256 * kMTopGroups) void mtransfer_up_kron_top(
     int nlev, const int64_t* __restrict__ lev, const int32_t* __restrict__ list, const int32_t* __restrict__ child0,
     const int32_t* __restrict__ child1, const float* __restrict__ E1, float* __restrict__ xhat) {
-  const int wave = threadIdx.x / 64, j = threadIdx.x % 64;
-  for (int l = nlev - 1; l >= 0; --l) {
-    if (j < 32 * NT)
-      for (int64_t w = lev[l] + wave; w < lev[l + 1]; w += kMTopWaves)
-        mup_kron<NT>(__builtin_amdgcn_readfirstlane(list[w]), j, child0, child1, E1, xhat);
-    __syncthreads();
-  }
+  __shared__ __attribute__((aligned(16))) float t[kMTopGroups * 2 * kTileFloats];
+  const int grp = threadIdx.x / 256, g = threadIdx.x % 256;
+  for (int l = nlev - 1; l >= 0; --l)
+    for (int64_t w0 = lev[l]; w0 < lev[l + 1]; w0 += kMTopGroups) {
+      const int64_t w = w0 + grp;
+      const int64_t c = w < lev[l + 1] ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[w])) : -1;
+      kup_group<NT>(c, g, child0, child1, E1, xhat, t + grp * 2 * kTileFloats);
+      __syncthreads();  // the tiles are read to the end before the next round fills them
+    }
 }
 
 template <int NT>
-__global__ __launch_bounds__(64 * kMTopWaves) void mtransfer_down_kron_top(int nlev, const int32_t* __restrict__ level_ptr,
+__global__ __launch_bounds__(256 * kMTopGroups) void mtransfer_down_kron_top(int nlev,
+                                                                           const int32_t* __restrict__ level_ptr,
                                                                            const int32_t* __restrict__ parent,
                                                                            const float* __restrict__ E1,
                                                                            float* __restrict__ yhat) {
-  const int wave = threadIdx.x / 64, j = threadIdx.x % 64;
-  for (int l = 0; l < nlev; ++l) {
-    if (j < 32 * NT)
-      for (int64_t c = level_ptr[l + 1] + wave; c < level_ptr[l + 2]; c += kMTopWaves) mdown_kron<NT>(c, j, parent, E1, yhat);
-    __syncthreads();
-  }
+  __shared__ __attribute__((aligned(16))) float t[kMTopGroups * kTileFloats];
+  const int grp = threadIdx.x / 256, g = threadIdx.x % 256;
+  for (int l = 0; l < nlev; ++l)
+    for (int64_t c0 = level_ptr[l + 1]; c0 < level_ptr[l + 2]; c0 += kMTopGroups) {
+      const int64_t c = c0 + grp < level_ptr[l + 2] ? c0 + grp : -1;
+      kdown_group<NT>(c, g, parent, E1, yhat, t + grp * kTileFloats);
+      __syncthreads();
+    }
 }
 
 // Y|tau = sum_{(tau,sigma) inadmissible} G|tau x sigma X|sigma + V_tau y^_tau for
@@ -910,45 +1031,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
 // complex: 16 complex columns jc held as 32 real columns j = 16 part + jc
 // (part 0 = real, 1 = imaginary); user vectors interleaved (re, im); tiled as above
 template <typename XT>
-__global__ __launch_bounds__(256) void mpermute_in_c(int64_t n, int rcur, const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(256) void mpermute_in_c(int64_t n, int rcur, const int32_t* __restrict__ iperm,
                                                      const XT* __restrict__ x, int64_t ldx, float* __restrict__ xc) {
+  constexpr int PER = 64 * 32 / 256;
   __shared__ float tile[64][33];
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
-  for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
-    const int part = idx % 2, pl = (idx / 2) % 64, jc = idx / 128;
-    const int64_t p = p0 + pl;
-    float v = 0.f;
-    if (jc < rcur && p < n) v = static_cast<float>(x[2 * (static_cast<int64_t>(jc) * ldx + perm[p]) + part]);
-    tile[pl][16 * part + jc] = v;
+  __shared__ int32_t pos[64];
+  const int t = threadIdx.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int32_t ip = iperm[min(i0 + t % 64, n - 1)];  // every wave loads the tile's positions
+  XT v[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int idx = t + 256 * s, part = idx % 2, il = (idx / 2) % 64, jc = idx / 128;
+    const bool ok = jc < rcur && i0 + il < n;
+    v[s] = x[ok ? 2 * (static_cast<int64_t>(jc) * ldx + i0 + il) + part : 0];
+    v[s] = ok ? v[s] : XT(0);
+  }
+  if (t < 64) pos[t] = i0 + t < n ? ip : 0;
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int idx = t + 256 * s, part = idx % 2, il = (idx / 2) % 64, jc = idx / 128;
+    tile[il][16 * part + jc] = static_cast<float>(v[s]);
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
-    const int pl = idx / 32, j = idx % 32;
-    const int64_t p = p0 + pl;
-    if (p < n) xc[p * 32 + j] = tile[pl][j];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int il = (t + 256 * s) / 32, j = (t + 256 * s) % 32;
+    if (i0 + il < n) xc[static_cast<int64_t>(pos[il]) * 32 + j] = tile[il][j];
   }
 }
 
 template <typename XT>
-__global__ __launch_bounds__(256) void mpermute_out_c(int64_t n, int rcur, const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(256) void mpermute_out_c(int64_t n, int rcur, const int32_t* __restrict__ iperm,
                                                       const float* __restrict__ yc, XT* __restrict__ y, int64_t ldy,
                                                       double alpha, bool ow) {
+  constexpr int PER = 64 * 32 / 256;
   __shared__ float tile[64][33];
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
-  for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
-    const int pl = idx / 32, j = idx % 32;
-    const int64_t p = p0 + pl;
-    tile[pl][j] = p < n ? yc[p * 32 + j] : 0.f;
+  __shared__ int32_t pos[64];
+  const int t = threadIdx.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int32_t ip = iperm[min(i0 + t % 64, n - 1)];  // every wave loads the tile's positions
+  XT y0[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int idx = t + 256 * s, part = idx % 2, il = (idx / 2) % 64, jc = idx / 128;
+    const bool ok = !ow && jc < rcur && i0 + il < n;
+    y0[s] = y[ok ? 2 * (static_cast<int64_t>(jc) * ldy + i0 + il) + part : 0];
+    y0[s] = ok ? y0[s] : XT(0);
   }
+  if (t < 64) pos[t] = i0 + t < n ? ip : 0;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
-    const int part = idx % 2, pl = (idx / 2) % 64, jc = idx / 128;
-    const int64_t p = p0 + pl;
-    if (jc < rcur && p < n) {
-      XT* dst = y + 2 * (static_cast<int64_t>(jc) * ldy + perm[p]) + part;
-      const double y0 = ow ? 0.0 : static_cast<double>(*dst);
-      *dst = static_cast<XT>(y0 + alpha * static_cast<double>(tile[pl][16 * part + jc]));
-    }
+  float v[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int il = (t + 256 * s) / 32, j = (t + 256 * s) % 32;
+    v[s] = yc[static_cast<int64_t>(pos[il]) * 32 + j];
+  }
+#pragma unroll
+  for (int s = 0; s < PER; ++s) tile[(t + 256 * s) / 32][(t + 256 * s) % 32] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int idx = t + 256 * s, part = idx % 2, il = (idx / 2) % 64, jc = idx / 128;
+    if (jc < rcur && i0 + il < n)
+      y[2 * (static_cast<int64_t>(jc) * ldy + i0 + il) + part] =
+          static_cast<XT>(static_cast<double>(y0[s]) + alpha * static_cast<double>(tile[il][16 * part + jc]));
   }
 }
 
@@ -1418,7 +1565,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     H2_HIP(hipEventRecord(e0, st));
   }
   const unsigned ptiles = nblk(n, 64);
-  mpermute_in<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), x, ldx, xc);
+  mpermute_in<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.iperm.as<int32_t>(), x, ldx, xc);
   mleaf_forward<NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                                H.cend.as<int32_t>(), H.Vf.as<float>(), xc, xh);
   const int up_top = H.kron ? H.mup_top : 0;  // the dense MFMA transfers run one launch per level
@@ -1426,7 +1573,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
     if (cnt == 0) continue;
     if (H.kron)
-      mtransfer_up_kron<NT><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
+      mtransfer_up_kron<NT><<<(cnt + 7) / 8 * 8, 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
                                                         H.child0.as<int32_t>(), H.child1.as<int32_t>(),
                                                         H.E1.as<float>(), xh);
     else
@@ -1434,7 +1581,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
                                                    H.child0.as<int32_t>(), H.child1.as<int32_t>(), H.ET.as<float>(), xh);
   }
   if (up_top > 0)
-    mtransfer_up_kron_top<NT><<<1, 64 * kMTopWaves, 0, st>>>(up_top, H.up_ptr_dev.as<int64_t>(),
+    mtransfer_up_kron_top<NT><<<1, 256 * kMTopGroups, 0, st>>>(up_top, H.up_ptr_dev.as<int64_t>(),
                                                              H.up_list.as<int32_t>(), H.child0.as<int32_t>(),
                                                              H.child1.as<int32_t>(), H.E1.as<float>(), xh);
   if (H.prof) {
@@ -1475,13 +1622,13 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
   }
   const int down_top = H.kron ? H.mdown_top : 0;
   if (down_top > 0)
-    mtransfer_down_kron_top<NT><<<1, 64 * kMTopWaves, 0, st>>>(down_top, H.level_ptr_dev.as<int32_t>(),
+    mtransfer_down_kron_top<NT><<<1, 256 * kMTopGroups, 0, st>>>(down_top, H.level_ptr_dev.as<int32_t>(),
                                                                H.parent.as<int32_t>(), H.E1.as<float>(), yh);
   for (int lv = down_top; lv < S.depth; ++lv) {
     const int first = S.level_ptr[lv + 1], cnt = S.level_ptr[lv + 2] - S.level_ptr[lv + 1];
     if (cnt == 0) continue;
     if (H.kron)
-      mtransfer_down_kron<NT><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.E1.as<float>(), yh);
+      mtransfer_down_kron<NT><<<(cnt + 7) / 8 * 8, 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.E1.as<float>(), yh);
     else
       mtransfer_down<NT><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
   }
@@ -1497,7 +1644,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
                                                         H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
                                                         H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
                                                         H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
-  mpermute_out<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
+  mpermute_out<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.iperm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
   H2_HIP(hipGetLastError());
   if (H.prof) {
     e4 = prof_event(H);
@@ -1531,14 +1678,14 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
     H2_HIP(hipEventRecord(e0, st));
   }
   const unsigned ptiles = nblk(n, 64);
-  mpermute_in_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), x, ldx, xc);
+  mpermute_in_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.iperm.as<int32_t>(), x, ldx, xc);
   mleaf_forward<1><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                               H.cend.as<int32_t>(), H.Vf.as<float>(), xc, xh);
   for (int lv = S.depth - 1; lv >= 0; --lv) {
     const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
     if (cnt == 0) continue;
     if (H.kron)
-      mtransfer_up_kron<1><<<grid8(cnt), 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
+      mtransfer_up_kron<1><<<(cnt + 7) / 8 * 8, 256, 0, st>>>(cnt, H.up_list.as<int32_t>() + H.up_ptr[lv],
                                                        H.child0.as<int32_t>(), H.child1.as<int32_t>(),
                                                        H.E1.as<float>(), xh);
     else
@@ -1566,7 +1713,7 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
     const int first = S.level_ptr[lv + 1], cnt = S.level_ptr[lv + 2] - S.level_ptr[lv + 1];
     if (cnt == 0) continue;
     if (H.kron)
-      mtransfer_down_kron<1><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.E1.as<float>(), yh);
+      mtransfer_down_kron<1><<<(cnt + 7) / 8 * 8, 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.E1.as<float>(), yh);
     else
       mtransfer_down<1><<<grid8(cnt), 256, 0, st>>>(first, cnt, H.parent.as<int32_t>(), H.F.as<float>(), yh);
   }
@@ -1578,7 +1725,7 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
                                                 H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
                                                 H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
                                                 H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
-  mpermute_out_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.perm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
+  mpermute_out_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.iperm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
   H2_HIP(hipGetLastError());
   if (H.prof) {
     e4 = prof_event(H);
