@@ -76,49 +76,6 @@ __device__ inline void mma64_rowA(const float* __restrict__ A, const float* __re
   }
 }
 
-// acc[ti][tj] += A(rows < mrows, kcount) * B(kcount, cols) with A column-major
-// (element (i, kk) at A[kk * lda + i]) and B position-major (element (kk, j) at
-// B[kk * ldb + j]); 1 <= kcount <= 64, mrows >= 1, lda * 64 and ldb * 64 fit in
-// int; rows >= mrows and kk >= kcount count as zero.  Lane half h covers
-// kk = step + 32 h; one load instruction reads one column (or row) of 32
-// consecutive elements per lane half.  Every load reads a clamped in-range
-// address and the mask is applied by a select, so the loop has no divergent
-// control flow.
-template <int NT>
-__device__ inline void mma_colA(const float* __restrict__ A, int lda, int mrows, const float* __restrict__ B,
-                                int ldb, int kcount, f32x16 (&acc)[2][NT]) {
-  const int l = threadIdx.x % 64, r = l % 32, h = l / 32;
-  const bool row0 = r < mrows, row1 = r + 32 < mrows;
-  const float* a0 = A + min(r, mrows - 1);
-  const float* a1 = A + min(r + 32, mrows - 1);
-  const float* b = B + r;
-  const int steps = min(32, kcount);
-#pragma unroll 2
-  for (int k0 = 0; k0 < steps; k0 += 4) {
-    float av[2][4], bv[NT][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int kk = k0 + u + 32 * h;
-      const bool ok = kk < kcount;
-      const int kc = min(kk, kcount - 1);
-      const float x0 = a0[kc * lda], x1 = a1[kc * lda];
-      av[0][u] = (ok && row0) ? x0 : 0.f;
-      av[1][u] = (ok && row1) ? x1 : 0.f;
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj) {
-        const float y = b[kc * ldb + 32 * tj];
-        bv[tj][u] = ok ? y : 0.f;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma(av[ti][u], bv[tj][u], acc[ti][tj]);
-  }
-}
-
 template <int NT>
 __device__ inline void zero(f32x16 (&acc)[2][NT]) {
 #pragma unroll
@@ -153,6 +110,13 @@ __device__ inline int64_t xcd_item(int64_t items) {
   const int64_t per = (nwg + 7) / 8;
   const int64_t wg = static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
   return __builtin_amdgcn_readfirstlane(static_cast<int>(wg * 4 + threadIdx.x / 64));  // 4 waves per workgroup
+}
+
+// item of a per-cluster workgroup: the grid (a multiple of 8 workgroups) in eight
+// chunks of consecutive items, one per XCD, so neighbouring clusters (siblings) share an L2
+__device__ inline int64_t xcd_group_item() {
+  const int64_t per = gridDim.x / 8;
+  return static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
 // ---------------------------------------------------------------- permutations
@@ -233,22 +197,79 @@ __global__ __launch_bounds__(256) void mpermute_out(int64_t n, int rcur, const i
 }
 
 // ---------------------------------------------------------------- phases (one wave per output block)
-// x^_sigma = V_sigma^T X|sigma (Alg. 1); A(nu, p) = Vf[p][nu] (column-major view)
+// x^_sigma = V_sigma^T X|sigma (Alg. 1) for every leaf (at most 64 triangles):
+// one workgroup per leaf.  The leaf's r x 64 block of V and r x RP block of X
+// are contiguous; they are moved to LDS with coalesced 16-byte loads (rows past r
+// as zeros), wave (ti, tj) forms the 32 x 32 tile D(nu, j) = sum_p V[p][nu] X[p][j]
+// (nu = 32 ti.., j = 32 tj..) with v_mfma_f32_32x32x2f32 straight from LDS (lane
+// l takes p = 2 s + l / 32; the pitch of 96 floats puts the two rows of a step in
+// different bank halves), and the tile leaves through LDS again as coalesced
+// 16-byte stores of the RP x 64 output.
+constexpr int kLeafPitch = 96;
+constexpr int kOutPitch = 68;
+
 template <int NT>
 __global__ __launch_bounds__(256) void mleaf_forward(int nleaves, const int32_t* __restrict__ leaves,
                                                      const int32_t* __restrict__ cbegin,
                                                      const int32_t* __restrict__ cend, const float* __restrict__ Vf,
                                                      const float* __restrict__ xc, float* __restrict__ xhat) {
-  const int64_t it = xcd_item((nleaves + 3) / 4 * 4);
-  if (it >= nleaves) return;
   constexpr int RP = 32 * NT;
-  const int32_t c = leaves[it];
-  const int64_t b0 = cbegin[c];
-  const int r = cend[c] - cbegin[c];
-  f32x16 acc[2][NT];
-  zero(acc);
-  mma_colA<NT>(Vf + b0 * 64, 64, 64, xc + b0 * RP, RP, r, acc);
-  store_hat<NT, false>(xhat + static_cast<int64_t>(c) * RP * 64, acc);
+  __shared__ __align__(16) float lds[2 * 64 * kLeafPitch];
+  float* vs = lds;
+  float* xs = lds + 64 * kLeafPitch;
+  const int64_t it = xcd_group_item();
+  if (it >= nleaves) return;  // whole workgroup
+  const int t = threadIdx.x;
+  const int32_t c = __builtin_amdgcn_readfirstlane(leaves[it]);
+  const int64_t b0 = __builtin_amdgcn_readfirstlane(cbegin[c]);
+  const int r = __builtin_amdgcn_readfirstlane(cend[c]) - static_cast<int>(b0);
+  f4v va[4], xa[RP / 16];
+  const f4v z4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int f = 4 * (q * 256 + t);
+    va[q] = f / 64 < r ? ld4c(Vf + b0 * 64 + f) : z4;
+  }
+#pragma unroll
+  for (int q = 0; q < RP / 16; ++q) {
+    const int f = 4 * (q * 256 + t);
+    xa[q] = f / RP < r ? ld4c(xc + b0 * RP + f) : z4;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int f = 4 * (q * 256 + t);
+    *reinterpret_cast<f4v*>(vs + (f / 64) * kLeafPitch + f % 64) = va[q];
+  }
+#pragma unroll
+  for (int q = 0; q < RP / 16; ++q) {
+    const int f = 4 * (q * 256 + t);
+    *reinterpret_cast<f4v*>(xs + (f / RP) * kLeafPitch + f % RP) = xa[q];
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(t / 64), l = t % 64;
+  const int ti = wave >> 1, tj = wave & 1;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  if (tj < NT) {
+    const float* a = vs + (l / 32) * kLeafPitch + 32 * ti + l % 32;
+    const float* b = xs + (l / 32) * kLeafPitch + 32 * tj + l % 32;
+    const int steps = (r + 1) / 2;  // row r, if read, is zero
+    for (int s = 0; s < steps; ++s) acc = mfma(a[2 * s * kLeafPitch], b[2 * s * kLeafPitch], acc);
+  }
+  __syncthreads();  // the operands' space is reused for the output tile
+  float* os = lds;  // os[j][nu], pitch kOutPitch
+  if (tj < NT) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) os[(32 * tj + l % 32) * kOutPitch + 32 * ti + acc_row(v, l)] = acc[v];
+  }
+  __syncthreads();
+  float* dst = xhat + static_cast<int64_t>(c) * RP * 64;
+#pragma unroll
+  for (int q = 0; q < RP / 16; ++q) {
+    const int f = 4 * (q * 256 + t);
+    *reinterpret_cast<f4v*>(dst + f) = *reinterpret_cast<const f4v*>(os + (f / 64) * kOutPitch + f % 64);
+  }
 }
 
 // x^_sigma = sum_children F^T x^_child; A(nu, nu') = ET[nu][nu'] (row-major)
@@ -346,6 +367,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
 #pragma unroll
     for (int q = 0; q < 4; ++q) reg[q] = ld4c(src + (q * 256 + t) * 4);
   };
+  // S is read once per pass: non-temporal loads keep it from displacing the x^
+  // tiles that other groups re-read from L2 (fetched bytes 1.46 -> 1.37 x S)
+  auto fetch_s = [&](const float* src, f4v(&reg)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reg[q] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(src + (q * 256 + t) * 4));
+  };
   auto put = [&](float* dst, const f4v(&reg)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -359,7 +386,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
     return en[1] >= 0 ? en[1] : en[2] >= 0 ? en[2] : en[3] >= 0 ? en[3] : en[4];
   };
   if (e0 < e1) {
-    fetch(S + static_cast<int64_t>(first_block(e0)) * 4096, sreg);
+    fetch_s(S + static_cast<int64_t>(first_block(e0)) * 4096, sreg);
     fetch(xhat + static_cast<int64_t>(ents[8 * e0]) * RP * 64, xreg);
     put(sbuf, sreg);
     put(xbuf, xreg);
@@ -378,7 +405,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
           if (blk[j] >= 0) nb = blk[j];
         const bool newx = nb < 0 && e + 1 < e1;
         if (newx) nb = first_block(e + 1);
-        if (nb >= 0) fetch(S + static_cast<int64_t>(nb) * 4096, sreg);
+        if (nb >= 0) fetch_s(S + static_cast<int64_t>(nb) * 4096, sreg);
         if (newx) fetch(xhat + static_cast<int64_t>(ents[8 * e + 8]) * RP * 64, xreg);
         mma_tile_k64(sbuf + (32 * ti + r) * kGrpPitch + 4 * h, xbuf + (32 * tj + r) * kGrpPitch + 4 * h, acc[i]);
         __syncthreads();  // every wave is done with this task's operands
@@ -705,13 +732,6 @@ __device__ inline void kdown_group(int64_t c, int g, const int32_t* __restrict__
   }
 }
 
-// item of a per-cluster workgroup: the grid (a multiple of 8 workgroups) in eight
-// chunks of consecutive items, one per XCD, so siblings share an L2
-__device__ inline int64_t xcd_group_item() {
-  const int64_t per = gridDim.x / 8;
-  return static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
-}
-
 // the parents of one level, one workgroup each
 template <int NT>
 __global__ __launch_bounds__(256) void mtransfer_up_kron(int count, const int32_t* __restrict__ list,
@@ -927,7 +947,7 @@ __device__ inline void near16_stream(const NearRow& d, const NearBlock* __restri
     for (int tj = 0; tj < TJ; ++tj) bv[tj] = B[16 * tj];
     const float* A = P + static_cast<int64_t>(cb + kc) * r;
 #pragma unroll
-    for (int ti = 0; ti < NTI; ++ti) av[ti] = A[rowc[ti]];
+    for (int ti = 0; ti < NTI; ++ti) av[ti] = __builtin_nontemporal_load(A + rowc[ti]);  // streamed once
     k0 += 4;
     if (k0 >= w) {
       k0 = 0;
@@ -1566,7 +1586,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
   }
   const unsigned ptiles = nblk(n, 64);
   mpermute_in<XT, RP><<<ptiles, 256, 0, st>>>(n, rcur, H.iperm.as<int32_t>(), x, ldx, xc);
-  mleaf_forward<NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+  mleaf_forward<NT><<<(nl + 7) / 8 * 8, 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                                H.cend.as<int32_t>(), H.Vf.as<float>(), xc, xh);
   const int up_top = H.kron ? H.mup_top : 0;  // the dense MFMA transfers run one launch per level
   for (int lv = S.depth - 1; lv >= up_top; --lv) {
@@ -1679,7 +1699,7 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
   }
   const unsigned ptiles = nblk(n, 64);
   mpermute_in_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.iperm.as<int32_t>(), x, ldx, xc);
-  mleaf_forward<1><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+  mleaf_forward<1><<<(nl + 7) / 8 * 8, 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
                                               H.cend.as<int32_t>(), H.Vf.as<float>(), xc, xh);
   for (int lv = S.depth - 1; lv >= 0; --lv) {
     const int cnt = static_cast<int>(H.up_ptr[lv + 1] - H.up_ptr[lv]);
