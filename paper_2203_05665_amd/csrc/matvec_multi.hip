@@ -904,20 +904,33 @@ __device__ inline void near16_leaf(int64_t it, int r, int64_t b0, int32_t tau, c
       }
 }
 
-// The same product with the K-steps of all the row's near blocks in one stream,
-// for rows of at most 64 near blocks: the wave holds the blocks' descriptors
-// (first triangle s0 and width w of sigma, first panel column cb) one per lane and
-// keeps NP K-steps in flight across block boundaries, so the pipeline never
-// drains between blocks.  A K-step past a block's last column re-reads that
-// column of the panel and multiplies it by a row of zeros instead of x, so no
-// loaded value needs a mask.
+// The same product with the K-steps of the row's near blocks in one stream, for
+// rows of at most 64 near blocks: the wave holds the blocks' descriptors (first
+// triangle s0 and width w of sigma, first panel column cb) one per lane and keeps
+// NP K-steps in flight across block boundaries, so the pipeline never drains
+// between blocks.  A K-step past a block's last column re-reads that column of
+// the panel and multiplies it by a row of zeros instead of x, so no loaded value
+// needs a mask.  Two waves share a leaf: half 0 streams the first ceil(nb / 2)
+// blocks, half 1 the rest and V_tau y^_tau, and half 1's sums reach half 0
+// through LDS (red, one 16 KB slot per leaf), which adds and stores them.  Half
+// the work per wave halves the tail of the launch (the last leaves to start run
+// alone): 2.07 -> 1.88 ms per 64-column pass on the 786k cube.
 __device__ float kZeroRow[64];  // zero-initialised, never written
 
 template <int TJ, int NTI>
-__device__ inline void near16_stream(const NearRow& d, const NearBlock* __restrict__ blocks, const float* __restrict__ N,
+__device__ inline void near16_stream(const NearRow& d0, int half, float* __restrict__ red,
+                                     const NearBlock* __restrict__ blocks, const float* __restrict__ N,
                                      const float* __restrict__ Vb, const float* __restrict__ xc,
                                      const float* __restrict__ yhat, float* __restrict__ yc) {
   constexpr int RP = 16 * TJ;
+  NearRow d = d0;
+  const int nb0 = (d0.nb + 1) / 2;
+  if (half == 0) {
+    d.nb = nb0;
+  } else {
+    d.bfirst += nb0;
+    d.nb = d0.nb - nb0;
+  }
   constexpr int NP = TJ >= 4 ? 3 : 4;  // K-steps in flight (within 128 VGPRs: four waves per SIMD)
   const int l = threadIdx.x % 64, li = l % 16, lk = l / 16;
   const int r = d.r;
@@ -977,7 +990,7 @@ __device__ inline void near16_stream(const NearRow& d, const NearBlock* __restri
   const float* A = Vb + static_cast<int64_t>(d.b0) * 64;
   const float* Y = yhat + static_cast<int64_t>(d.tau) * RP * 64 + li * 64;
 #pragma unroll 2
-  for (int q0 = 0; q0 < 64; q0 += 4) {
+  for (int q0 = 0; q0 < (half ? 64 : 0); q0 += 4) {
     const int kk = q0 + lk;
     float a2[NTI], b2[TJ];
 #pragma unroll
@@ -989,6 +1002,17 @@ __device__ inline void near16_stream(const NearRow& d, const NearBlock* __restri
 #pragma unroll
       for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = mfma16(a2[ti], b2[tj], acc[ti][tj]);
   }
+  // the two halves' sums: half 1 hands its registers over through LDS
+  if (half == 1) {
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((ti * TJ + tj) * 4 + v) * 64 + l] = acc[ti][tj][v];
+  }
+  __syncthreads();
+  if (half == 1) return;
   float* out = yc + static_cast<int64_t>(d.b0) * RP + li;
 #pragma unroll
   for (int ti = 0; ti < NTI; ++ti)
@@ -997,7 +1021,7 @@ __device__ inline void near16_stream(const NearRow& d, const NearBlock* __restri
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * ti + 4 * lk + v;
-        if (i < r) out[i * RP + 16 * tj] = acc[ti][tj][v];
+        if (i < r) out[i * RP + 16 * tj] = acc[ti][tj][v] + red[((ti * TJ + tj) * 4 + v) * 64 + l];
       }
 }
 
@@ -1006,16 +1030,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
     int nleaves, const NearRow* __restrict__ rows, const NearBlock* __restrict__ blocks, const float* __restrict__ N,
     const float* __restrict__ Vb, const float* __restrict__ xc, const float* __restrict__ yhat,
     float* __restrict__ yc) {
-  // one leaf per wave: its index is wave-uniform, so the row, the block
-  // descriptors and the step iterator live in scalar registers
-  const int it = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_item(nleaves)));
-  if (it >= nleaves) return;
+  // two leaves per workgroup, two waves per leaf; the halves of a leaf meet at
+  // one workgroup barrier, which the waves of a missing second leaf also reach
+  __shared__ __align__(16) float red[2][4 * TJ * 4 * 64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t it = xcd_group_item() * 2 + (wave >> 1);
+  const int half = wave & 1;
+  if (it >= nleaves) {
+    __syncthreads();
+    return;
+  }
   const NearRow d = rows[it];
+  float* rd = red[wave >> 1];
   switch ((d.r + 15) >> 4) {  // wave-uniform: one leaf per wave
-    case 1: near16_stream<TJ, 1>(d, blocks, N, Vb, xc, yhat, yc); break;
-    case 2: near16_stream<TJ, 2>(d, blocks, N, Vb, xc, yhat, yc); break;
-    case 3: near16_stream<TJ, 3>(d, blocks, N, Vb, xc, yhat, yc); break;
-    default: near16_stream<TJ, 4>(d, blocks, N, Vb, xc, yhat, yc); break;
+    case 1: near16_stream<TJ, 1>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
+    case 2: near16_stream<TJ, 2>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
+    case 3: near16_stream<TJ, 3>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
+    default: near16_stream<TJ, 4>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
   }
 }
 
@@ -1657,7 +1688,7 @@ void run_pass(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64_t
     H2_HIP(hipEventRecord(e3, st));
   }
   if (H.near_row64)
-    mnear_stream16<2 * NT><<<grid8(nl), 256, 0, st>>>(nl, H.near_rows.as<NearRow>(), H.near_blocks.as<NearBlock>(),
+    mnear_stream16<2 * NT><<<((nl + 1) / 2 + 7) / 8 * 8, 256, 0, st>>>(nl, H.near_rows.as<NearRow>(), H.near_blocks.as<NearBlock>(),
                                                       H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
   else
     mnear_backward16<2 * NT><<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
