@@ -1486,8 +1486,8 @@ std::vector<int32_t> interleaved_rows(const Structure& S) {
 // The groups of mcoupling_grp: the four grandchildren of every cluster whose two
 // children both have children, then the remaining row clusters in runs of up to
 // four consecutive ids; sorted by first row, cut into 8 contiguous chunks of about
-// equal work (blocks + 1 per group), one per XCD, each padded with empty groups to
-// the common length.  Entries: (column cluster, block of each slot or -1, 3 x
+// equal work (blocks + 1 per group), one per XCD, each ordered heaviest first and
+// padded with empty groups to the common length.  Entries: (column cluster, block of each slot or -1, 3 x
 // padding), per group ordered by the position of the column cluster.
 void build_groups(h2_handle_s& H) {
   const Structure& S = H.S;
@@ -1554,10 +1554,21 @@ void build_groups(h2_handle_s& H) {
   for (int c = 0; c < 8; ++c) L = std::max<int64_t>(L, cut[c + 1] - cut[c]);
   std::vector<int32_t> rows(8 * L * 4, -1), ents;
   std::vector<int64_t> ptr(8 * L + 1, 0);
+  // within a chunk the groups go out heaviest first (the workgroups of an XCD
+  // take them in dispatch order): in tree order the heavy groups that start last
+  // set the end of the launch (simulated makespan 1.26 x the mean work per
+  // slot, 1.07 x heaviest first); the x^ tiles of the groups in flight are then
+  // less often shared (fetched 1.37 -> 1.48 x S), and the coupling still drops
+  // from 3.32 to 3.11 ms on the 786k cube
+  std::vector<int64_t> order(ng);
+  for (int64_t gi = 0; gi < ng; ++gi) order[gi] = gi;
+  for (int c = 0; c < 8; ++c)
+    std::stable_sort(order.begin() + cut[c], order.begin() + cut[c + 1],
+                     [&](int64_t a, int64_t b) { return work[a] > work[b]; });
   for (int c = 0; c < 8; ++c)
     for (int64_t q = 0; q < L; ++q) {
-      const int64_t slot = c * L + q, gi = cut[c] + q;
-      if (gi < cut[c + 1]) {
+      const int64_t slot = c * L + q, gi = cut[c] + q < cut[c + 1] ? order[cut[c] + q] : ng;
+      if (gi < ng) {
         for (int i = 0; i < 4; ++i) rows[4 * slot + i] = groups[gi][i];
         ents.insert(ents.end(), ge[gi].begin(), ge[gi].end());
       }
