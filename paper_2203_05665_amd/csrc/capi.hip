@@ -178,6 +178,13 @@ int build_h2(const h2_mesh* mesh, const h2_params* params, h2_handle* out) {
           H->up_ptr[l + 1] = static_cast<int64_t>(ul.size());
         }
         H->up_list.upload(ul);
+        {
+          std::vector<h2::RowSpan> sp(S.nclusters);
+          for (int32_t c = 0; c < S.nclusters; ++c)
+            sp[c] = {S.adm_ptr[c], static_cast<int32_t>(S.adm_ptr[c + 1] - S.adm_ptr[c]), c};
+          std::stable_sort(sp.begin(), sp.end(), [](const h2::RowSpan& a, const h2::RowSpan& b) { return a.nb > b.nb; });
+          H->row_spans.upload(sp);
+        }
         // levels with few clusters from the root down: their transfers run in one workgroup
         auto top_levels = [&](int64_t most, bool up) {
           int t = 0;

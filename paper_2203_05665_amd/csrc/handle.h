@@ -68,6 +68,14 @@ struct NearBlock {
   int32_t s0, w, cb, pad;
 };
 
+// One row cluster of the single-vector coupling evaluated during the product: its
+// first admissible block, its block count and its id.  The table lists the rows
+// heaviest first.
+struct RowSpan {
+  int64_t b0;
+  int32_t nb, tau;
+};
+
 // bf16 storage element (upper half of an IEEE float).
 struct bf16 {
   uint16_t v;
@@ -92,6 +100,9 @@ struct h2_handle_s {
   // block); near64: every leaf holds at most 64 triangles and every row at most 256
   // near blocks, so that kernel applies
   h2::DBuf near_rows, near_blocks;
+  // the rows of the single-vector coupling evaluated during the product, heaviest
+  // first (h2::RowSpan)
+  h2::DBuf row_spans;
   bool near64 = false;
   bool near_row64 = false;  // also at most 64 near blocks per row (mnear_stream16 applies)
   // on-the-fly coupling: cluster centres (FP64, 3 per cluster) and point offsets from

@@ -1444,9 +1444,10 @@ inline unsigned nblk(int64_t work, int per) {
 
 // Row clusters for the coupling kernels: 8 contiguous ranges of about equal
 // work (admissible blocks + 1 per row), one per XCD (xcd_item gives XCD x the
-// items [x L, (x + 1) L)), each padded with -1 to the common length L, a
-// multiple of 4.  Contiguous ranges keep neighbouring rows, which share column
-// clusters, on one L2; equal work keeps the eight XCDs busy until the end.
+// items [x L, (x + 1) L)), each ordered heaviest first and padded with -1 to the
+// common length L, a multiple of 4.  Contiguous ranges keep neighbouring rows,
+// which share column clusters, on one L2; equal work keeps the eight XCDs busy
+// until the end, and heaviest first keeps a heavy row from starting last.
 std::vector<int32_t> balanced_rows(const Structure& S) {
   const int32_t nc = S.nclusters;
   double total = 0.0;
@@ -1463,8 +1464,14 @@ std::vector<int32_t> balanced_rows(const Structure& S) {
   for (int c = 0; c < 8; ++c) L = std::max<int64_t>(L, cut[c + 1] - cut[c]);
   L = (L + 3) / 4 * 4;
   std::vector<int32_t> order(8 * L, -1);
-  for (int c = 0; c < 8; ++c)
+  for (int c = 0; c < 8; ++c) {
     for (int32_t t = cut[c]; t < cut[c + 1]; ++t) order[c * L + (t - cut[c])] = t;
+    // heaviest rows of the chunk first, so that no heavy row starts last
+    std::stable_sort(order.begin() + c * L, order.begin() + c * L + (cut[c + 1] - cut[c]),
+                     [&](int32_t a, int32_t b) {
+                       return S.adm_ptr[a + 1] - S.adm_ptr[a] > S.adm_ptr[b + 1] - S.adm_ptr[b];
+                     });
+  }
   return order;
 }
 
