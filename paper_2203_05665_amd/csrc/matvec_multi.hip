@@ -1436,6 +1436,144 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
   }
 }
 
+// The complex near field streamed as near16_stream does for the real one (rows
+// of at most 64 near blocks, K-steps across block boundaries, two waves per leaf
+// meeting through LDS): the panel entry (re, im) is one 8-byte load per row and
+// K-step, and the products accumulate straight into the output's two parts,
+// Yr += Re(A) Xr - Im(A) Xi and Yi += Re(A) Xi + Im(A) Xr (tile tj = 0: Xr, 1: Xi),
+// so one accumulator pair per row tile holds the result.
+template <int NTI>
+__device__ inline void near16c_stream(const NearRow& d0, int half, float* __restrict__ red,
+                                      const NearBlock* __restrict__ blocks, const float* __restrict__ N,
+                                      const float* __restrict__ Vb, const float* __restrict__ xc,
+                                      const float* __restrict__ yhat, float* __restrict__ yc) {
+  NearRow d = d0;
+  const int nb0 = (d0.nb + 1) / 2;
+  if (half == 0) {
+    d.nb = nb0;
+  } else {
+    d.bfirst += nb0;
+    d.nb = d0.nb - nb0;
+  }
+  constexpr int NP = 4;  // K-steps in flight
+  const int l = threadIdx.x % 64, li = l % 16, lk = l / 16;
+  const int r = d.r;
+  int rowc[NTI];
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti) rowc[ti] = min(16 * ti + li, r - 1);  // rows past r are computed, not stored
+  f4v yr[NTI], yi[NTI];
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti) yr[ti] = yi[ti] = f4v{0.f, 0.f, 0.f, 0.f};
+  NearBlock e{0, 1, 0, 0};
+  if (l < d.nb) e = blocks[d.bfirst + l];
+  int nst = l < d.nb ? (e.w + 3) >> 2 : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nst += __shfl_xor(nst, o);
+  nst = __builtin_amdgcn_readfirstlane(nst);
+  const float* P = N + 2 * d.panel_off;
+  int m = 0, k0 = 0;
+  int s0 = __builtin_amdgcn_readlane(e.s0, 0), w = __builtin_amdgcn_readlane(e.w, 0);
+  int cb = __builtin_amdgcn_readlane(e.cb, 0);
+  auto fetch = [&](f2v (&av)[NTI], float (&bv)[2]) {
+    const int kk = k0 + lk;
+    const int kc = min(kk, w - 1);
+    const float* B = (m < d.nb && kk < w) ? xc + static_cast<int64_t>(s0 + kk) * 32 + li : kZeroRow + li;
+    bv[0] = B[0];
+    bv[1] = B[16];
+    const float* A = P + 2 * static_cast<int64_t>(cb + kc) * r;
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti) av[ti] = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(A + 2 * rowc[ti]));
+    k0 += 4;
+    if (k0 >= w) {
+      k0 = 0;
+      if (++m < d.nb) {
+        s0 = __builtin_amdgcn_readlane(e.s0, m);
+        w = __builtin_amdgcn_readlane(e.w, m);
+        cb = __builtin_amdgcn_readlane(e.cb, m);
+      }
+    }
+  };
+  f2v av[NP][NTI];
+  float bv[NP][2];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) fetch(av[q], bv[q]);
+  for (int st = 0; st < nst; st += NP) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int ti = 0; ti < NTI; ++ti) {
+        yr[ti] = mfma16(av[q][ti].x, bv[q][0], yr[ti]);
+        yr[ti] = mfma16(-av[q][ti].y, bv[q][1], yr[ti]);
+        yi[ti] = mfma16(av[q][ti].x, bv[q][1], yi[ti]);
+        yi[ti] = mfma16(av[q][ti].y, bv[q][0], yi[ti]);
+      }
+      fetch(av[q], bv[q]);
+    }
+  }
+  // + V_tau [y^r | y^i] (the second half)
+  const float* A = Vb + static_cast<int64_t>(d.b0) * 64;
+  const float* Y = yhat + static_cast<int64_t>(d.tau) * 32 * 64 + li * 64;
+#pragma unroll 2
+  for (int q0 = 0; q0 < (half ? 64 : 0); q0 += 4) {
+    const int kk = q0 + lk;
+    const float br = Y[kk], bi = Y[16 * 64 + kk];
+    float a2[NTI];
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti) a2[ti] = A[kk * r + rowc[ti]];
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti) {
+      yr[ti] = mfma16(a2[ti], br, yr[ti]);
+      yi[ti] = mfma16(a2[ti], bi, yi[ti]);
+    }
+  }
+  // half 1 hands its sums over through LDS
+  if (half == 1) {
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        red[((ti * 2 + 0) * 4 + v) * 64 + l] = yr[ti][v];
+        red[((ti * 2 + 1) * 4 + v) * 64 + l] = yi[ti][v];
+      }
+  }
+  __syncthreads();
+  if (half == 1) return;
+  float* out = yc + static_cast<int64_t>(d.b0) * 32 + li;
+#pragma unroll
+  for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * ti + 4 * lk + v;
+      if (i < r) {
+        out[i * 32] = yr[ti][v] + red[((ti * 2 + 0) * 4 + v) * 64 + l];
+        out[i * 32 + 16] = yi[ti][v] + red[((ti * 2 + 1) * 4 + v) * 64 + l];
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mnear_stream16c(
+    int nleaves, const NearRow* __restrict__ rows, const NearBlock* __restrict__ blocks, const float* __restrict__ N,
+    const float* __restrict__ Vb, const float* __restrict__ xc, const float* __restrict__ yhat,
+    float* __restrict__ yc) {
+  // two leaves per workgroup, two waves per leaf, as mnear_stream16
+  __shared__ __align__(16) float red[2][4 * 2 * 4 * 64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t it = xcd_group_item() * 2 + (wave >> 1);
+  const int half = wave & 1;
+  if (it >= nleaves) {
+    __syncthreads();
+    return;
+  }
+  const NearRow d = rows[it];
+  float* rd = red[wave >> 1];
+  switch ((d.r + 15) >> 4) {
+    case 1: near16c_stream<1>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
+    case 2: near16c_stream<2>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
+    case 3: near16c_stream<3>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
+    default: near16c_stream<4>(d, half, rd, blocks, N, Vb, xc, yhat, yc); break;
+  }
+}
+
 inline unsigned nblk(int64_t work, int per) {
   const int64_t g = (work + per - 1) / per;
   if (g > 0x7fffffff) throw Error(H2_EINVAL, "launch too large");
@@ -1447,7 +1585,10 @@ inline unsigned nblk(int64_t work, int per) {
 // items [x L, (x + 1) L)), each ordered heaviest first and padded with -1 to the
 // common length L, a multiple of 4.  Contiguous ranges keep neighbouring rows,
 // which share column clusters, on one L2; equal work keeps the eight XCDs busy
-// until the end, and heaviest first keeps a heavy row from starting last.
+// until the end, and heaviest first keeps a heavy row from starting last
+// (mcoupling_otf 3.07 -> 2.66 ms on the 786k cube with 64 columns; the complex
+// coupling 5.03 -> 4.85 ms stored and 3.47 -> 2.71 ms on the fly at 327,680
+// triangles with 16 complex columns).
 std::vector<int32_t> balanced_rows(const Structure& S) {
   const int32_t nc = S.nclusters;
   double total = 0.0;
@@ -1466,7 +1607,6 @@ std::vector<int32_t> balanced_rows(const Structure& S) {
   std::vector<int32_t> order(8 * L, -1);
   for (int c = 0; c < 8; ++c) {
     for (int32_t t = cut[c]; t < cut[c + 1]; ++t) order[c * L + (t - cut[c])] = t;
-    // heaviest rows of the chunk first, so that no heavy row starts last
     std::stable_sort(order.begin() + c * L, order.begin() + c * L + (cut[c + 1] - cut[c]),
                      [&](int32_t a, int32_t b) {
                        return S.adm_ptr[a + 1] - S.adm_ptr[a] > S.adm_ptr[b + 1] - S.adm_ptr[b];
@@ -1790,10 +1930,15 @@ void run_pass_c(h2_handle_s& H, int rcur, const XT* x, int64_t ldx, XT* y, int64
     e3 = prof_event(H);
     H2_HIP(hipEventRecord(e3, st));
   }
-  mnear_backward16c<<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
-                                                H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
-                                                H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
-                                                H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
+  if (H.near_row64)
+    mnear_stream16c<<<((nl + 1) / 2 + 7) / 8 * 8, 256, 0, st>>>(nl, H.near_rows.as<NearRow>(),
+                                                               H.near_blocks.as<NearBlock>(), H.Nmat.as<float>(),
+                                                               H.Vb.as<float>(), xc, yh, yc);
+  else
+    mnear_backward16c<<<grid8(nl), 256, 0, st>>>(nl, H.leaves.as<int32_t>(), H.cbegin.as<int32_t>(),
+                                                  H.cend.as<int32_t>(), H.near_ptr.as<int64_t>(),
+                                                  H.near_col.as<int32_t>(), H.panel_off.as<int64_t>(),
+                                                  H.Nmat.as<float>(), H.Vb.as<float>(), xc, yh, yc);
   mpermute_out_c<XT><<<ptiles, 256, 0, st>>>(n, rcur, H.iperm.as<int32_t>(), yc, y, ldy, alpha, H.overwrite);
   H2_HIP(hipGetLastError());
   if (H.prof) {
