@@ -205,3 +205,30 @@ def test_helmholtz_otf_full_size_sphere327k():
         assert np.linalg.norm(Yo[:, j] - Ys[:, j]) <= 2e-6 * scale[j], j
         bounds.check(Yo[:, j], Ys[:, j], 2 * SC[:, j], "f32", "Helmholtz 327k otf vs stored col %d" % j,
                      t_rel=1e-5)
+
+
+def test_helmholtz_multi_rhs_fallback_near():
+    """A row with 68 near blocks (1,280 triangles, leaf size 6) takes the
+    per-block complex near field (mnear_backward16c) for several columns, the
+    structures of the other tests (at most 44 near blocks per row) the streamed
+    one (mnear_stream16c)."""
+    kind, level, m, leaf, kappa = "sphere", 3, 4, 6, 4.0
+    H = oracle(kind, level, m, leaf, HELMHOLTZ, kappa)
+    L = oracle(kind, level, m, leaf, LAPLACE, 0.0)
+    rng = np.random.default_rng(11)
+    n, nrhs = H.mesh.n, 2
+    X = rng.standard_normal((n, nrhs)) + 1j * rng.standard_normal((n, nrhs))
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, kernel="helmholtz", kappa=kappa, order=m, leaf=leaf, eta=0.5,
+                    storage="f32")
+    try:
+        xd = torch.tensor(X, device="cuda").t().contiguous().t()
+        yd = torch.zeros_like(xd)
+        A.matvec(xd, yd)
+        Y = yd.cpu().numpy()
+    finally:
+        A.close()
+    for j in range(nrhs):
+        gx = H.matvec(X[:, j])
+        scale = L.matvec(np.abs(X[:, j]))
+        assert np.linalg.norm(Y[:, j] - gx) <= 1e-6 * np.linalg.norm(scale), j
+        bounds.check(Y[:, j], gx, scale, "f32", "Helmholtz multi fallback near col %d" % j)
