@@ -771,7 +771,7 @@ __global__ __launch_bounds__(256 * kMTopGroups) void mtransfer_up_kron_top(
       const int64_t w = w0 + grp;
       const int64_t c = w < lev[l + 1] ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[w])) : -1;
       kup_group<NT>(c, g, child0, child1, E1, xhat, t + grp * 2 * kTileFloats);
-      __syncthreads();  // the tiles are read to the end before the next round fills them
+      __syncthreads();  // the tiles are read to the end before the next clusters fill them
     }
 }
 
