@@ -137,7 +137,7 @@ def test_helmholtz_cg_is_rejected():
 
 
 @pytest.mark.parametrize("otf", [False, True])
-@pytest.mark.parametrize("case", [("sphere", 3, 4, 16, 4.0), ("cube", 16, 4, 64, 2.0)])
+@pytest.mark.parametrize("case", [("sphere", 3, 4, 16, 4.0), ("cube", 16, 4, 64, 2.0), ("cube", 10, 4, 32, 4.0)])
 @pytest.mark.parametrize("nrhs", [2, 5, 16, 17, 33])
 def test_helmholtz_multi_rhs(case, nrhs, otf):
     """Complex many-RHS product on the matrix cores: every column against the oracle."""

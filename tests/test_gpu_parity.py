@@ -227,6 +227,32 @@ def test_multi_rhs_matches_oracle(case, nrhs, otf):
                      extra=4.5e-16 * np.abs(Y0[:, j]))
 
 
+@pytest.mark.parametrize("case", [("cube", 10, 4, 32), ("cube", 5, 4, 16), ("sphere", 1, 4, 8), ("cube", 2, 4, 16)])
+@pytest.mark.parametrize("nrhs", [3, 64])
+def test_multi_rhs_ragged_sizes(case, nrhs):
+    """Many right-hand sides on meshes whose triangle count is not a multiple of
+    the 64 user indices one permutation workgroup moves (1,200, 300, 80 and 48
+    triangles: the last tile is partial, and on the smallest meshes it is the only
+    one), with the leaves' rows and the coupling's groups as ragged as they come."""
+    kind, level, m, leaf = case
+    H = oracle(kind, level, m, leaf)
+    n = H.mesh.n
+    assert n % 64 != 0
+    X = I.random_vector(n, 31, "normal", nrhs=nrhs)
+    A = h2.H2Matrix(H.mesh.V, H.mesh.T, order=m, leaf=leaf, eta=0.5, storage="f32")
+    try:
+        xd = torch.tensor(X, dtype=torch.float64, device="cuda").t().contiguous().t()
+        yd = torch.zeros_like(xd)
+        A.matvec(xd, yd)
+        torch.cuda.synchronize()
+        Y = yd.cpu().numpy()
+    finally:
+        A.close()
+    for j in (0, nrhs - 1):
+        bounds.check(Y[:, j], H.matvec(X[:, j]), H.matvec(np.abs(X[:, j])), "f32",
+                     "ragged multi %s%d R=%d col %d" % (kind, level, nrhs, j))
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("case", [("sphere", 3, 3, 32), ("sphere", 3, 4, 16), ("cube", 16, 4, 32),
                                   ("sphere", 2, 5, 40)])
