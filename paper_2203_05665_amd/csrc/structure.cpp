@@ -4,6 +4,7 @@
 #include "structure.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 #include <stdexcept>
@@ -21,6 +22,9 @@ struct Node {
 // Work below this many triangles (tree) or pairs (block tree) stays on the
 // calling thread; above it the two halves of a split run on two threads.
 constexpr int32_t kParallelTriangles = 1 << 15;
+// A cluster of at least this many triangles also splits its own passes (the
+// bounding boxes, the count and the stable partition) over the threads it has.
+constexpr int32_t kParallelPasses = 1 << 16;
 
 int worker_threads() {
   const unsigned h = std::thread::hardware_concurrency();
@@ -43,6 +47,20 @@ void parallel_for(int64_t n, int threads, F&& f) {
   for (auto& t : pool) t.join();
 }
 
+// runs f(w) for w in [0, nw): w = 0 on the calling thread, the rest on threads
+// of their own
+template <class F>
+void run_chunks(int nw, F&& f) {
+  if (nw <= 1) {
+    f(0);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back([&, w]() { f(w); });
+  f(0);
+  for (auto& t : pool) t.join();
+}
+
 struct TreeBuilder {
   const double* V;
   const int32_t* T;
@@ -55,62 +73,102 @@ struct TreeBuilder {
   // The index ranges of two children are disjoint, so with par_depth > 0 the
   // subtree of child 0 is built on a second thread into a vector of its own and
   // both are appended in pre-order afterwards: the same tree, node for node.
-  int32_t build(std::vector<Node>& out, int32_t begin, int32_t end, int32_t level, int32_t parent, int par_depth) {
+  // A large cluster also runs its own passes on its nthr threads, in contiguous
+  // chunks: minima, maxima and counts do not depend on how the range is cut, and
+  // each chunk writes its low and high triangles at offsets given by the counts
+  // of the chunks before it, which is the sequential stable partition.  The
+  // bounding box of the triangles is formed at the leaves and, for the other
+  // clusters, as the union of the two children's boxes (the same minima and
+  // maxima), so the vertices are read once per triangle, not once per level.
+  int32_t build(std::vector<Node>& out, int32_t begin, int32_t end, int32_t level, int32_t parent, int par_depth,
+                int nthr) {
     const int32_t id = static_cast<int32_t>(out.size());
     out.push_back(Node{begin, end, level, parent, {-1, -1}, {0, 0, 0}, {0, 0, 0}});
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int32_t p = begin; p < end; ++p) {
-      const int32_t t = idx[p];
-      for (int a = 0; a < 3; ++a) {
-        const double* v = V + 3 * static_cast<int64_t>(T[3 * static_cast<int64_t>(t) + a]);
-        for (int d = 0; d < 3; ++d) {
-          lo[d] = std::min(lo[d], v[d]);
-          hi[d] = std::max(hi[d], v[d]);
+    const int32_t size = end - begin;
+    const int nw = size >= kParallelPasses ? std::max(1, nthr) : 1;
+    auto lo_of = [&](int w) { return begin + static_cast<int32_t>(static_cast<int64_t>(size) * w / nw); };
+    // a leaf: the bounding box of its triangles' vertices
+    auto leaf_box = [&]() {
+      for (int d = 0; d < 3; ++d) {
+        out[id].lo[d] = INFINITY;
+        out[id].hi[d] = -INFINITY;
+      }
+      for (int32_t p = begin; p < end; ++p) {
+        const int32_t t = idx[p];
+        for (int a = 0; a < 3; ++a) {
+          const double* v = V + 3 * static_cast<int64_t>(T[3 * static_cast<int64_t>(t) + a]);
+          for (int d = 0; d < 3; ++d) {
+            out[id].lo[d] = std::min(out[id].lo[d], v[d]);
+            out[id].hi[d] = std::max(out[id].hi[d], v[d]);
+          }
         }
       }
-    }
-    for (int d = 0; d < 3; ++d) {
-      out[id].lo[d] = lo[d];
-      out[id].hi[d] = hi[d];
-    }
-    const int32_t size = end - begin;
-    if (size <= leaf) return id;
-    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int32_t p = begin; p < end; ++p) {
-      const double* c = &cen[3 * static_cast<int64_t>(idx[p])];
-      for (int d = 0; d < 3; ++d) {
-        clo[d] = std::min(clo[d], c[d]);
-        chi[d] = std::max(chi[d], c[d]);
+      return id;
+    };
+    if (size <= leaf) return leaf_box();
+    // the bounding box of the centroids
+    std::vector<std::array<double, 6>> box(nw);
+    run_chunks(nw, [&](int w) {
+      double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+      for (int32_t p = lo_of(w); p < lo_of(w + 1); ++p) {
+        const double* c = &cen[3 * static_cast<int64_t>(idx[p])];
+        for (int d = 0; d < 3; ++d) {
+          clo[d] = std::min(clo[d], c[d]);
+          chi[d] = std::max(chi[d], c[d]);
+        }
       }
-    }
+      for (int d = 0; d < 3; ++d) {
+        box[w][d] = clo[d];
+        box[w][3 + d] = chi[d];
+      }
+    });
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int w = 0; w < nw; ++w)
+      for (int d = 0; d < 3; ++d) {
+        clo[d] = std::min(clo[d], box[w][d]);
+        chi[d] = std::max(chi[d], box[w][3 + d]);
+      }
     int axis = 0;
     double ext[3] = {chi[0] - clo[0], chi[1] - clo[1], chi[2] - clo[2]};
     for (int d = 1; d < 3; ++d)
       if (ext[d] > ext[axis]) axis = d;
-    if (!(ext[axis] > 0.0)) return id;
+    if (!(ext[axis] > 0.0)) return leaf_box();
     const double mid = 0.5 * (clo[axis] + chi[axis]);
-    int32_t nlow = 0;
-    for (int32_t p = begin; p < end; ++p)
-      if (cen[3 * static_cast<int64_t>(idx[p]) + axis] < mid) ++nlow;
-    if (nlow == 0 || nlow == size) return id;
+    std::vector<int32_t> lowc(nw + 1, 0);
+    run_chunks(nw, [&](int w) {
+      int32_t c = 0;
+      for (int32_t p = lo_of(w); p < lo_of(w + 1); ++p)
+        if (cen[3 * static_cast<int64_t>(idx[p]) + axis] < mid) ++c;
+      lowc[w + 1] = c;
+    });
+    for (int w = 0; w < nw; ++w) lowc[w + 1] += lowc[w];
+    const int32_t nlow = lowc[nw];
+    if (nlow == 0 || nlow == size) return leaf_box();
     // stable partition: low side first, both sides keep their relative order
-    int32_t a = begin, b = begin + nlow;
-    for (int32_t p = begin; p < end; ++p) {
-      const int32_t t = idx[p];
-      if (cen[3 * static_cast<int64_t>(t) + axis] < mid) tmp[a++] = t; else tmp[b++] = t;
-    }
-    std::copy(tmp.begin() + begin, tmp.begin() + end, idx.begin() + begin);
+    run_chunks(nw, [&](int w) {
+      int32_t a = begin + lowc[w], b = begin + nlow + (lo_of(w) - begin - lowc[w]);
+      for (int32_t p = lo_of(w); p < lo_of(w + 1); ++p) {
+        const int32_t t = idx[p];
+        if (cen[3 * static_cast<int64_t>(t) + axis] < mid) tmp[a++] = t; else tmp[b++] = t;
+      }
+    });
+    run_chunks(nw, [&](int w) { std::copy(tmp.begin() + lo_of(w), tmp.begin() + lo_of(w + 1), idx.begin() + lo_of(w)); });
     int32_t c0, c1;
     if (par_depth > 0 && size >= kParallelTriangles) {
       std::vector<Node> v0, v1;
-      std::thread th([&]() { build(v0, begin, begin + nlow, level + 1, -1, par_depth - 1); });
-      build(v1, begin + nlow, end, level + 1, -1, par_depth - 1);
+      const int n0 = std::max(1, nthr / 2), n1 = std::max(1, nthr - nthr / 2);
+      std::thread th([&]() { build(v0, begin, begin + nlow, level + 1, -1, par_depth - 1, n0); });
+      build(v1, begin + nlow, end, level + 1, -1, par_depth - 1, n1);
       th.join();
       c0 = append(out, v0, id);
       c1 = append(out, v1, id);
     } else {
-      c0 = build(out, begin, begin + nlow, level + 1, id, 0);
-      c1 = build(out, begin + nlow, end, level + 1, id, 0);
+      c0 = build(out, begin, begin + nlow, level + 1, id, 0, 1);
+      c1 = build(out, begin + nlow, end, level + 1, id, 0, 1);
+    }
+    for (int d = 0; d < 3; ++d) {
+      out[id].lo[d] = std::min(out[c0].lo[d], out[c1].lo[d]);
+      out[id].hi[d] = std::max(out[c0].hi[d], out[c1].hi[d]);
     }
     out[id].child[0] = c0;
     out[id].child[1] = c1;
@@ -269,7 +327,7 @@ void build_structure(Structure& S, const double* vertices, int64_t nv, const int
   std::vector<Node> nodes;
   int par_depth = 0;
   while ((1 << par_depth) < threads) ++par_depth;
-  tb.build(nodes, 0, static_cast<int32_t>(nt), 0, -1, par_depth);
+  tb.build(nodes, 0, static_cast<int32_t>(nt), 0, -1, par_depth, threads);
   S.perm = tb.idx;
 
   // renumber breadth first (stable within a level = depth-first order)
