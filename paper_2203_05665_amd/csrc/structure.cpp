@@ -289,7 +289,7 @@ void csr_by_row(const Pairs& pairs, int32_t nrows, std::vector<int64_t>& ptr, st
   col.resize(pairs.size());
   std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
   for (const auto& pr : pairs) col[fill[pr.first]++] = pr.second;
-  for (int32_t i = 0; i < nrows; ++i) std::sort(col.begin() + ptr[i], col.begin() + ptr[i + 1], less);
+  parallel_for(nrows, worker_threads(), [&](int64_t i) { std::sort(col.begin() + ptr[i], col.begin() + ptr[i + 1], less); });
 }
 
 }  // namespace
