@@ -52,11 +52,14 @@ __device__ inline void kernel_eval(const KernelFn kf, double x0, double x1, doub
     return;
   }
   const double d0 = x0 - y0, d1 = x1 - y1, d2 = x2 - y2;
-  const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-  const double inv = 1.0 / (4.0 * kPi * r);
+  const double q = d0 * d0 + d1 * d1 + d2 * d2;
+  // one reciprocal square root instead of a square root and a division (the
+  // FP64 assembly's most expensive steps; both within a few ulp)
+  const double rinv = rsqrt(q);
+  const double inv = rinv * (1.0 / (4.0 * kPi));
   if (kf.kind == H2_HELMHOLTZ) {
     double sn, cs;
-    sincos(kf.kappa * r, &sn, &cs);
+    sincos(kf.kappa * (q * rinv), &sn, &cs);
     re = cs * inv;
     im = sn * inv;
   } else {
