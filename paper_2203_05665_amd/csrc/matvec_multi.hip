@@ -9,12 +9,14 @@
 //   x_c, y_c   [n][RP]        position-major, right-hand sides contiguous
 //   x^, y^     [N_c][RP][k]   per cluster, the k coefficients of one right-hand
 //                             side contiguous
-// One wave owns one output block (a row cluster, a leaf or a transfer target)
-// and computes all of it: 2 x (RP/32) tiles of 32 x 32 (rows of k or of the leaf
-// x right-hand sides), so every input element is loaded once per block.  Row
-// clusters are dealt to the eight XCDs in contiguous chunks, so neighbouring
-// rows, which share most of their column clusters, share an L2.  Every output
-// element has one owner: no atomics.
+// One wave or one workgroup owns one output block (a row cluster or a group of
+// four, a leaf, a transfer target) and computes all of it, so every input
+// element is loaded once per block: the coupling and the leaf forward on 32 x 32
+// tiles, the near field on 16 x 16 tiles (two waves per leaf), the Kronecker
+// transfers with four waves per cluster.  Rows, leaves and clusters are dealt to
+// the eight XCDs in contiguous chunks, so neighbouring ones, which share most of
+// their column clusters, share an L2.  Every output element has one owner: no
+// atomics.
 //
 // MFMA operand convention (K = 64 per call, split across lane halves): in each
 // step lanes 0-31 supply A[i][kk] and B[kk][j] for one kk of the first half of K
