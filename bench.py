@@ -732,6 +732,11 @@ def main():
             yy = torch.zeros_like(x)
             elv, _ = measure(M, x, yy, max(3, args.steps // 2), 1, torch, h2)
             mv = max(3, args.steps // 2) / elv
+            # a few untimed steps first: the solver's workspace and kernels are set up
+            # on the handle's first solve (about 0.1 s once per process and handle)
+            z = torch.zeros_like(bd)
+            h2.h2_solve(M.h, bd, z, method="cg", rtol=1e-8, maxit=3, refine=st_name != "f64", inner_rtol=1e-4,
+                        check=False)
             z = torch.zeros_like(bd)
             torch.cuda.synchronize()
             info_s = h2.h2_solve(M.h, bd, z, method="cg", rtol=1e-8, maxit=2000, refine=st_name != "f64",
