@@ -77,6 +77,34 @@ def test_structure_equals_oracle(which):
         h2.h2_free(hdl)
 
 
+@pytest.mark.parametrize("mesh", [("sphere", 6), ("cube", 96)])
+def test_cluster_tree_with_split_passes_equals_oracle(mesh):
+    """Meshes of 81,920 and 110,592 triangles: their top clusters hold more than
+    65,536 triangles, so the host builder splits each one's passes (centroid box,
+    count, stable partition) over its threads and forms the vertex boxes at the
+    leaves, merged upwards.  The tree must still be the oracle's, triangle order
+    and boxes bit for bit."""
+    from oracle.h2 import H2Oracle
+    from oracle.kernels import Kernel
+    V, T = I.mesh_for(*mesh)
+    assert T.shape[0] > 65536
+    H = H2Oracle(V, T, Kernel(), m=4, leaf=64, eta=0.5, build_blocks=False)
+    hdl = h2.build_h2(V, T, order=4, leaf=64, eta=0.5, host_only=True)
+    try:
+        tr = H.tree
+        assert h2.h2_info(hdl)["nclusters"] == len(tr.clusters)
+        assert np.array_equal(h2.h2_export(hdl, h2.H2_X_PERM), tr.perm)
+        cl = h2.h2_export(hdl, h2.H2_X_CLUSTERS).reshape(-1, 6)
+        bx = h2.h2_export(hdl, h2.H2_X_BOXES).reshape(-1, 6)
+        dfs = h2.h2_export(hdl, h2.H2_X_DFS)
+        for c in range(cl.shape[0]):
+            o = tr.clusters[dfs[c]]
+            assert (o.begin, o.end, o.level) == (cl[c, 0], cl[c, 1], cl[c, 5])
+            assert np.array_equal(bx[c, :3], o.lo) and np.array_equal(bx[c, 3:], o.hi)
+    finally:
+        h2.h2_free(hdl)
+
+
 def test_structure_counts_at_full_size():
     """1,310,720-triangle sphere, m = 4, leaf 64: the trees build on the host and
     every index lands in exactly one leaf."""
